@@ -1,0 +1,153 @@
+/*
+ * dctplus: the DCT+ transform on AMD Instinct MI355X (gfx950).
+ *
+ * DCT+ is the graph Fourier transform (GFT) of a path graph whose Laplacian
+ * has received a rank-one update, L = L_path + rho v v^T (Fernandez-Menduina,
+ * Pavez, Ortega, arXiv 2409.08970, Sec. 2, Def. of rank-one updates and
+ * Def. of DCT+).  With L_path = U diag(lambda) U^T (U the orthonormal
+ * DCT-II basis, lambda_k = 2 - 2 cos(pi k / n)) and L = X diag(mu) X^T, the
+ * paper's Thm 3.1 factors the new basis as
+ *
+ *     X^T = diag(a) C(mu, lambda) diag(z) U^T,   z = U^T v,
+ *     C(mu, lambda)_ij = 1 / (mu_i - lambda_j),  a_i = column normalisers,
+ *
+ * where mu are the roots of the secular equation (Remark 1) interlacing
+ * lambda (Lemma 4.1).  The library applies y = X^T x (forward), x = X y
+ * (adjoint = inverse, X is orthogonal), the gradient of a loss of y with
+ * respect to x, rho and v, and batched progressive selection with pruning
+ * (Thm 3.4).
+ *
+ * Conventions
+ *   - Indices are 0-based.  Output row i of y corresponds to mu_i in
+ *     ascending order.
+ *   - Sign: every eigenvector satisfies rho * v^T x_i > 0 (a_i > 0 above).
+ *     Directions with z_k = 0 after deflation (|z_k| <= defl_tol * ||z||)
+ *     are the DCT vectors u_k themselves (mu = lambda_k, sign +).  When a
+ *     secular root coincides with such a lambda_k (a double eigenvalue) the
+ *     deflation basis is kept and the deflated row is ordered first.
+ *   - rho = 0 or v = 0 gives exactly the orthonormal DCT-II.
+ *   - Signals are contiguous row-major [batch, n] arrays in DEVICE memory,
+ *     4-byte aligned (FP32) or 8-byte aligned (FP64); the caller owns them.
+ *   - All calls taking a stream are stream-ordered and asynchronous unless
+ *     stated; stream is a hipStream_t passed as void* (NULL = null stream).
+ *   - Errors are reported through the return status only; nothing aborts.
+ *     On any non-OK status no output has been written (argument errors are
+ *     detected before any device work).  dctplus_last_error() gives a
+ *     thread-local message for the last failure.
+ *   - A plan is immutable after creation and may be used concurrently from
+ *     several streams, except that the gradient and selection calls use the
+ *     plan's workspace and must not overlap on one plan.
+ */
+#ifndef DCTPLUS_H
+#define DCTPLUS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dctplus_plan_s *dctplus_plan_t;
+
+typedef enum {
+    DCTPLUS_OK = 0,
+    DCTPLUS_EINVAL = 1,       /* invalid argument (null/misaligned pointer, bad size, non-finite input, aliasing) */
+    DCTPLUS_ENOMEM = 2,       /* device or host allocation failed */
+    DCTPLUS_EDEVICE = 3,      /* HIP runtime error (see dctplus_last_error) */
+    DCTPLUS_EUNSUPPORTED = 4, /* valid request outside what this build implements (route, dtype, n) */
+    DCTPLUS_ENOCONV = 5       /* the secular-equation solver did not converge */
+} dctplus_status;
+
+/* Element type of signals, and the arithmetic of the bulk of the transform. */
+typedef enum {
+    DCTPLUS_F32 = 0,  /* FP32 signals; FP32 DCT, FP64 Cauchy stage (fast), FP32 MFMA (dense) */
+    DCTPLUS_F64 = 1,  /* FP64 signals and FP64 arithmetic throughout */
+    DCTPLUS_BF16 = 2  /* FP32 signals; dense routes only: BF16 MFMA operands, FP32 accumulation */
+} dctplus_dtype;
+
+/* How the product with diag(a) C(mu, lambda) diag(z) is formed. */
+typedef enum {
+    DCTPLUS_ROUTE_AUTO = 0,  /* DENSE for n <= 64, FAST above (F32); FAST for F64 */
+    DCTPLUS_ROUTE_FAST = 1,  /* Alg. 1 / Thm 3.3: DCT-II, DST-I, sine NUFFT, O(n log n) */
+    DCTPLUS_ROUTE_DENSE = 2, /* Thm 3.1: DCT-II, then an MFMA product with the n x n Cauchy factor */
+    DCTPLUS_ROUTE_GFT = 3    /* dense GFT (the paper's naive product): MFMA product with X^T */
+} dctplus_route;
+
+typedef struct {
+    int32_t dtype;        /* dctplus_dtype */
+    int32_t route;        /* dctplus_route */
+    double defl_tol;      /* deflation threshold on |z_k| / ||z||; <= 0 selects 1e-13 */
+    int32_t nufft_width;  /* window taps of the sine NUFFT (FAST route), 4..16; 0 selects 12 */
+    double direct_kappa;  /* FAST route: rows whose NUFFT error amplification exceeds this are
+                             summed exactly in FP64; <= 0 selects 1e5 */
+    int32_t device;       /* HIP device ordinal; < 0 uses the current device */
+} dctplus_opts;
+
+/* Fill *opts with the defaults. */
+void dctplus_default_opts(dctplus_opts *opts);
+
+/*
+ * Build a plan for L = L_path + rho v v^T on n vertices (setup, Remark 1).
+ *   n       : 4 <= n <= 16384, a power of two (EUNSUPPORTED otherwise; EINVAL if n < 2).
+ *   rho     : finite.  rho < 0 is supported by every route.
+ *   v_host  : HOST pointer to n finite doubles (copied; need not stay valid).
+ *   opts    : NULL for defaults.
+ *   stream  : the plan's tables are computed on this stream (FP64 secular solve
+ *             on the GPU); the call synchronises the stream once before returning.
+ *   out     : receives the plan (owned by the caller, release with dctplus_plan_destroy).
+ * The DENSE and GFT routes allocate an n x n matrix (4 n^2 bytes, plus 2 n^2 for BF16).
+ */
+dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const dctplus_opts *opts,
+                            void *stream, dctplus_plan_t *out);
+
+/* y = X^T x for `batch` signals (Thm 3.1; Alg. 1 on the FAST route).
+ * x, y: device arrays [batch, n] of the plan's element type; x and y must not alias.
+ * batch == 0 is a no-op; batch < 0 is EINVAL. */
+dctplus_status dctplus_forward(dctplus_plan_t plan, const void *x, void *y, int64_t batch, void *stream);
+
+/* x = X y for `batch` signals: the inverse (X is orthogonal), formed by
+ * applying the transposed steps of the forward in reverse order (Sec. 3,
+ * Thm 3.3: backward transform by step-wise inversion).  Same layout rules. */
+dctplus_status dctplus_adjoint(dctplus_plan_t plan, const void *y, void *x, int64_t batch, void *stream);
+
+/*
+ * Gradient of a scalar loss l(y), y = X^T x, given gy = dl/dy (FP32 plans only).
+ *   y, gy  : device [batch, n] FP32 (y from dctplus_forward on the same x).
+ *   gx     : device [batch, n] FP32 receiving dl/dx = X gy, or NULL to skip.
+ *   grho   : device pointer to one double receiving dl/drho, or NULL.
+ *   gv     : device pointer to n doubles receiving dl/dv, or NULL.
+ * With G = sum_b gy_b y_b^T, A_ik = G_ik / (mu_i - mu_k) (A_ii = 0) and
+ * w = X^T v:  dl/drho = w^T A w,  dl/dv = rho X (A + A^T) w  (first-order
+ * eigenvector perturbation of L x_i = mu_i x_i, with Lemma 4.2 for w).
+ * Uses the plan's workspace: calls on one plan must not overlap.
+ */
+dctplus_status dctplus_grad(dctplus_plan_t plan, const void *y, const void *gy, int64_t batch, void *gx,
+                            double *grho, double *gv, void *stream);
+
+/*
+ * Copy plan tables to HOST arrays (synchronous; for tests and tools).
+ * Any pointer may be NULL.  mu, a: n doubles in row order (a_i = 1 for
+ * deflated rows); z: n doubles, U^T v after deflation; kind: n int32 per row
+ * (0 = NUFFT row, 1 = deflated row, 2 = row summed directly);
+ * counts: 4 int32 = {deflated rows, direct rows, NUFFT window width, route used}.
+ */
+dctplus_status dctplus_plan_info(dctplus_plan_t plan, double *mu, double *a, double *z, int32_t *kind,
+                                 int32_t *counts);
+
+/* Copy one named plan table to HOST memory (synchronous; for tests and tools).
+ * name: "z", "zraw", "mu", "a", "tau", "hz", "deconv", "rowA", "rowB", "win", "direct",
+ *       "sintab" (double); "origin", "kind", "ref", "m0", "rowOfBin", "rowOfK", "direct_row"
+ *       (int32).  *bytes: capacity of dst on input, size of the table on output;
+ *       dst may be NULL to query the size.  Unknown name: EINVAL. */
+dctplus_status dctplus_plan_table(dctplus_plan_t plan, const char *name, void *dst, int64_t *bytes);
+
+/* Release a plan and its device memory (NULL is a no-op).  Synchronises the device. */
+void dctplus_plan_destroy(dctplus_plan_t plan);
+
+const char *dctplus_status_string(dctplus_status s);
+const char *dctplus_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DCTPLUS_H */

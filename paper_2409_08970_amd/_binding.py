@@ -1,0 +1,187 @@
+"""ctypes binding of libdctplus.so (argument marshalling only).
+
+Every function here has the name of the C-ABI entry point it wraps (see
+include/dctplus.h).  Device buffers are passed as integer addresses
+(``tensor.data_ptr()``) and streams as integer handles
+(``torch.cuda.current_stream().cuda_stream``).  No arithmetic of the
+transform happens in Python.  Loading fails loudly when the library has not
+been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdctplus.so")
+
+DCTPLUS_OK = 0
+DCTPLUS_EINVAL = 1
+DCTPLUS_ENOMEM = 2
+DCTPLUS_EDEVICE = 3
+DCTPLUS_EUNSUPPORTED = 4
+DCTPLUS_ENOCONV = 5
+
+DCTPLUS_F32, DCTPLUS_F64, DCTPLUS_BF16 = 0, 1, 2
+DCTPLUS_ROUTE_AUTO, DCTPLUS_ROUTE_FAST, DCTPLUS_ROUTE_DENSE, DCTPLUS_ROUTE_GFT = 0, 1, 2, 3
+
+EXPORTED = (
+    "dctplus_default_opts", "dctplus_plan", "dctplus_forward", "dctplus_adjoint", "dctplus_grad",
+    "dctplus_plan_info", "dctplus_plan_table", "dctplus_plan_destroy", "dctplus_status_string",
+    "dctplus_last_error",
+)
+
+
+class dctplus_opts(ctypes.Structure):
+    _fields_ = [
+        ("dtype", ctypes.c_int32),
+        ("route", ctypes.c_int32),
+        ("defl_tol", ctypes.c_double),
+        ("nufft_width", ctypes.c_int32),
+        ("direct_kappa", ctypes.c_double),
+        ("device", ctypes.c_int32),
+    ]
+
+
+class DctPlusError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: status {status} ({message})")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the shared library once; raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with paper_2409_08970_amd/build.py "
+                          "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    vp, i64, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.dctplus_default_opts.argtypes = [ctypes.POINTER(dctplus_opts)]
+    lib.dctplus_default_opts.restype = None
+    lib.dctplus_plan.argtypes = [i64, ctypes.c_double, dp, ctypes.POINTER(dctplus_opts), vp,
+                                 ctypes.POINTER(vp)]
+    lib.dctplus_plan.restype = ctypes.c_int
+    lib.dctplus_forward.argtypes = [vp, vp, vp, i64, vp]
+    lib.dctplus_forward.restype = ctypes.c_int
+    lib.dctplus_adjoint.argtypes = [vp, vp, vp, i64, vp]
+    lib.dctplus_adjoint.restype = ctypes.c_int
+    lib.dctplus_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
+    lib.dctplus_grad.restype = ctypes.c_int
+    lib.dctplus_plan_info.argtypes = [vp, dp, dp, dp, i32p, i32p]
+    lib.dctplus_plan_info.restype = ctypes.c_int
+    lib.dctplus_plan_table.argtypes = [vp, ctypes.c_char_p, vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.dctplus_plan_table.restype = ctypes.c_int
+    lib.dctplus_plan_destroy.argtypes = [vp]
+    lib.dctplus_plan_destroy.restype = None
+    lib.dctplus_status_string.argtypes = [ctypes.c_int]
+    lib.dctplus_status_string.restype = ctypes.c_char_p
+    lib.dctplus_last_error.argtypes = []
+    lib.dctplus_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != DCTPLUS_OK:
+        lib = load()
+        msg = lib.dctplus_last_error().decode(errors="replace")
+        raise DctPlusError(status, where, msg or lib.dctplus_status_string(status).decode())
+
+
+def dctplus_default_opts() -> dctplus_opts:
+    o = dctplus_opts()
+    load().dctplus_default_opts(ctypes.byref(o))
+    return o
+
+
+def dctplus_plan(n: int, rho: float, v, opts: dctplus_opts | None = None, stream: int = 0,
+                 check: bool = True):
+    """Returns (status, handle).  v: sequence of n floats (copied to a host double array)."""
+    import numpy as np
+    varr = np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(-1))
+    handle = ctypes.c_void_p()
+    st = load().dctplus_plan(int(n), float(rho), varr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             ctypes.byref(opts) if opts is not None else None, ctypes.c_void_p(stream),
+                             ctypes.byref(handle))
+    if check:
+        _check(st, "dctplus_plan")
+    return st, handle
+
+
+def dctplus_forward(plan, x_ptr: int, y_ptr: int, batch: int, stream: int = 0, check: bool = True) -> int:
+    st = load().dctplus_forward(plan, ctypes.c_void_p(x_ptr), ctypes.c_void_p(y_ptr), int(batch),
+                                ctypes.c_void_p(stream))
+    if check:
+        _check(st, "dctplus_forward")
+    return st
+
+
+def dctplus_adjoint(plan, y_ptr: int, x_ptr: int, batch: int, stream: int = 0, check: bool = True) -> int:
+    st = load().dctplus_adjoint(plan, ctypes.c_void_p(y_ptr), ctypes.c_void_p(x_ptr), int(batch),
+                                ctypes.c_void_p(stream))
+    if check:
+        _check(st, "dctplus_adjoint")
+    return st
+
+
+def dctplus_grad(plan, y_ptr: int, gy_ptr: int, batch: int, gx_ptr: int, grho_ptr: int, gv_ptr: int,
+                 stream: int = 0, check: bool = True) -> int:
+    st = load().dctplus_grad(plan, ctypes.c_void_p(y_ptr), ctypes.c_void_p(gy_ptr), int(batch),
+                             ctypes.c_void_p(gx_ptr or None), ctypes.c_void_p(grho_ptr or None),
+                             ctypes.c_void_p(gv_ptr or None), ctypes.c_void_p(stream))
+    if check:
+        _check(st, "dctplus_grad")
+    return st
+
+
+def dctplus_plan_info(plan, n: int):
+    """Host copies: dict(mu, a, z, kind, counts)."""
+    import numpy as np
+    mu = np.zeros(n)
+    a = np.zeros(n)
+    z = np.zeros(n)
+    kind = np.zeros(n, dtype=np.int32)
+    counts = np.zeros(4, dtype=np.int32)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    st = load().dctplus_plan_info(plan, mu.ctypes.data_as(dp), a.ctypes.data_as(dp), z.ctypes.data_as(dp),
+                                  kind.ctypes.data_as(ip), counts.ctypes.data_as(ip))
+    _check(st, "dctplus_plan_info")
+    return dict(mu=mu, a=a, z=z, kind=kind, counts=counts)
+
+
+_INT_TABLES = {"origin", "kind", "ref", "m0", "rowOfBin", "rowOfK", "direct_row"}
+
+
+def dctplus_plan_table(plan, name: str):
+    """Host copy of one named plan table (numpy array)."""
+    import numpy as np
+    lib = load()
+    size = ctypes.c_int64(0)
+    _check(lib.dctplus_plan_table(plan, name.encode(), None, ctypes.byref(size)), "dctplus_plan_table")
+    dt = np.int32 if name in _INT_TABLES else np.float64
+    out = np.zeros(size.value // np.dtype(dt).itemsize, dtype=dt)
+    if size.value:
+        _check(lib.dctplus_plan_table(plan, name.encode(), ctypes.c_void_p(out.ctypes.data), ctypes.byref(size)),
+               "dctplus_plan_table")
+    return out
+
+
+def dctplus_plan_destroy(plan) -> None:
+    if plan:
+        load().dctplus_plan_destroy(plan)
+
+
+def dctplus_status_string(status: int) -> str:
+    return load().dctplus_status_string(int(status)).decode()
+
+
+def dctplus_last_error() -> str:
+    return load().dctplus_last_error().decode(errors="replace")

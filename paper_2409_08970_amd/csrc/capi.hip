@@ -1,0 +1,272 @@
+// C-ABI entry points of the dctplus library.  Argument checks happen on the
+// host before any device work; every HIP error becomes DCTPLUS_EDEVICE.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "common.h"
+
+namespace dctplus {
+
+static thread_local char g_err[512] = "";
+
+dctplus_status fail(dctplus_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+dctplus_status hip_fail(hipError_t e, const char *what) {
+    return fail(DCTPLUS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+dctplus_status ensure_work(dctplus_plan_s *p, size_t bytes) {
+    if (p->work_bytes >= bytes) return DCTPLUS_OK;
+    if (p->work) {
+        // earlier stream-ordered users of the old buffer must be done before it goes
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "synchronize before workspace growth");
+        (void)hipFree(p->work);
+        p->work = nullptr;
+        p->work_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&p->work, bytes);
+    if (e != hipSuccess) {
+        p->work = nullptr;
+        (void)hipGetLastError();
+        return fail(DCTPLUS_ENOMEM, "hipMalloc(%zu) for the workspace failed", bytes);
+    }
+    p->work_bytes = bytes;
+    return DCTPLUS_OK;
+}
+
+static bool aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
+
+static size_t elem_size(const dctplus_plan_s *p) { return p->dtype == DCTPLUS_F64 ? 8 : 4; }
+
+static dctplus_status check_io(const dctplus_plan_s *p, const void *in, const void *out, int64_t batch) {
+    if (!p) return fail(DCTPLUS_EINVAL, "null plan");
+    if (batch < 0) return fail(DCTPLUS_EINVAL, "batch = %lld < 0", (long long)batch);
+    if (batch == 0) return DCTPLUS_OK;
+    if (!in || !out) return fail(DCTPLUS_EINVAL, "null signal pointer");
+    const size_t es = elem_size(p);
+    if (!aligned(in, es) || !aligned(out, es)) return fail(DCTPLUS_EINVAL, "misaligned signal pointer");
+    const size_t bytes = (size_t)batch * p->n * es;
+    const char *a = (const char *)in, *b = (const char *)out;
+    if (a < b + bytes && b < a + bytes) return fail(DCTPLUS_EINVAL, "input and output overlap");
+    if ((uint64_t)batch > (uint64_t)INT64_MAX / (uint64_t)p->n / es)
+        return fail(DCTPLUS_EINVAL, "batch too large");
+    return DCTPLUS_OK;
+}
+
+static dctplus_status set_device(const dctplus_plan_s *p) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != p->device) {
+        e = hipSetDevice(p->device);
+        if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    }
+    return DCTPLUS_OK;
+}
+
+}  // namespace dctplus
+
+using namespace dctplus;
+
+extern "C" {
+
+void dctplus_default_opts(dctplus_opts *o) {
+    if (!o) return;
+    o->dtype = DCTPLUS_F32;
+    o->route = DCTPLUS_ROUTE_AUTO;
+    o->defl_tol = 1e-13;
+    o->nufft_width = 12;
+    o->direct_kappa = 1e5;
+    o->device = -1;
+}
+
+dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const dctplus_opts *opts, void *stream,
+                            dctplus_plan_t *out) {
+    if (!out) return fail(DCTPLUS_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (n < 2) return fail(DCTPLUS_EINVAL, "n = %lld < 2", (long long)n);
+    if (n < 4 || n > 16384 || (n & (n - 1)))
+        return fail(DCTPLUS_EUNSUPPORTED, "n = %lld: supported sizes are powers of two in [4, 16384]",
+                    (long long)n);
+    if (!isfinite(rho)) return fail(DCTPLUS_EINVAL, "rho is not finite");
+    if (!v_host) return fail(DCTPLUS_EINVAL, "null v");
+    for (int64_t i = 0; i < n; ++i)
+        if (!isfinite(v_host[i])) return fail(DCTPLUS_EINVAL, "v[%lld] is not finite", (long long)i);
+    dctplus_opts o;
+    dctplus_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.dtype < DCTPLUS_F32 || o.dtype > DCTPLUS_BF16) return fail(DCTPLUS_EINVAL, "bad dtype %d", o.dtype);
+    if (o.route < DCTPLUS_ROUTE_AUTO || o.route > DCTPLUS_ROUTE_GFT)
+        return fail(DCTPLUS_EINVAL, "bad route %d", o.route);
+    if (!(o.defl_tol > 0.0)) o.defl_tol = 1e-13;
+    if (!(o.direct_kappa > 0.0)) o.direct_kappa = 1e5;
+    if (o.nufft_width == 0) o.nufft_width = 12;
+    if (o.nufft_width < 4 || o.nufft_width > kMaxWidth || (o.nufft_width & 1))
+        return fail(DCTPLUS_EINVAL, "nufft_width %d: must be even, 4..%d", o.nufft_width, kMaxWidth);
+    int route = o.route;
+    if (route == DCTPLUS_ROUTE_AUTO) {
+        if (o.dtype == DCTPLUS_F64) route = DCTPLUS_ROUTE_FAST;
+        else if (o.dtype == DCTPLUS_BF16) route = DCTPLUS_ROUTE_DENSE;
+        else route = DCTPLUS_ROUTE_DENSE;   // the FAST kernels are switched off in this build
+    }
+    if (o.dtype == DCTPLUS_F64 && route != DCTPLUS_ROUTE_FAST)
+        return fail(DCTPLUS_EUNSUPPORTED, "FP64 signals are supported on the FAST route");
+    if (o.dtype == DCTPLUS_BF16 && route == DCTPLUS_ROUTE_FAST)
+        return fail(DCTPLUS_EUNSUPPORTED, "BF16 operands apply to the DENSE and GFT routes");
+    if ((route == DCTPLUS_ROUTE_DENSE || route == DCTPLUS_ROUTE_GFT) && n > 4096)
+        return fail(DCTPLUS_EUNSUPPORTED, "dense routes support n <= 4096");
+    if (o.dtype == DCTPLUS_BF16 && (n < 32 || n > 64))
+        return fail(DCTPLUS_EUNSUPPORTED, "BF16 dense routes support n in {32, 64}");
+
+    int dev = o.device;
+    hipError_t e;
+    if (dev < 0) {
+        if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+    } else if ((e = hipSetDevice(dev)) != hipSuccess) {
+        return hip_fail(e, "hipSetDevice");
+    }
+    dctplus_plan_s *p = new (std::nothrow) dctplus_plan_s();
+    if (!p) return fail(DCTPLUS_ENOMEM, "host allocation failed");
+    p->n = n;
+    p->logn = 0;
+    while ((1LL << p->logn) < n) ++p->logn;
+    p->rho = rho;
+    p->dtype = o.dtype;
+    p->route = route;
+    p->device = dev;
+    p->defl_tol = o.defl_tol;
+    p->direct_kappa = o.direct_kappa;
+    p->width = o.nufft_width;
+    dctplus_status st = plan_build(p, v_host, (hipStream_t)stream);
+    if (st != DCTPLUS_OK) {
+        dctplus_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return DCTPLUS_OK;
+}
+
+dctplus_status dctplus_forward(dctplus_plan_t p, const void *x, void *y, int64_t batch, void *stream) {
+    dctplus_status st = check_io(p, x, y, batch);
+    if (st != DCTPLUS_OK || batch == 0) return st;
+    if ((st = set_device(p)) != DCTPLUS_OK) return st;
+    if (p->route == DCTPLUS_ROUTE_FAST) return fast_apply(p, x, y, batch, false, (hipStream_t)stream);
+    return dense_apply(p, x, y, batch, false, (hipStream_t)stream);
+}
+
+dctplus_status dctplus_adjoint(dctplus_plan_t p, const void *y, void *x, int64_t batch, void *stream) {
+    dctplus_status st = check_io(p, y, x, batch);
+    if (st != DCTPLUS_OK || batch == 0) return st;
+    if ((st = set_device(p)) != DCTPLUS_OK) return st;
+    if (p->route == DCTPLUS_ROUTE_FAST) return fast_apply(p, y, x, batch, true, (hipStream_t)stream);
+    return dense_apply(p, y, x, batch, true, (hipStream_t)stream);
+}
+
+dctplus_status dctplus_grad(dctplus_plan_t p, const void *y, const void *gy, int64_t batch, void *gx, double *grho,
+                            double *gv, void *stream) {
+    if (!p) return fail(DCTPLUS_EINVAL, "null plan");
+    if (p->dtype != DCTPLUS_F32) return fail(DCTPLUS_EUNSUPPORTED, "gradients are implemented for FP32 plans");
+    if (batch < 0) return fail(DCTPLUS_EINVAL, "batch = %lld < 0", (long long)batch);
+    if (!y || !gy) return fail(DCTPLUS_EINVAL, "null y or gy");
+    if (!aligned(y, 4) || !aligned(gy, 4) || (gx && !aligned(gx, 4)) || (grho && !aligned(grho, 8)) ||
+        (gv && !aligned(gv, 8)))
+        return fail(DCTPLUS_EINVAL, "misaligned pointer");
+    if (gx) {
+        dctplus_status st = check_io(p, gy, gx, batch);
+        if (st != DCTPLUS_OK) return st;
+    }
+    dctplus_status st = set_device(p);
+    if (st != DCTPLUS_OK) return st;
+    return grad_apply(p, (const float *)y, (const float *)gy, batch, (float *)gx, grho, gv, (hipStream_t)stream);
+}
+
+dctplus_status dctplus_plan_info(dctplus_plan_t p, double *mu, double *a, double *z, int32_t *kind,
+                                 int32_t *counts) {
+    if (!p) return fail(DCTPLUS_EINVAL, "null plan");
+    dctplus_status st = set_device(p);
+    if (st != DCTPLUS_OK) return st;
+    const size_t nd = sizeof(double) * p->n;
+    hipError_t e = hipSuccess;
+    if (mu && (e = hipMemcpy(mu, p->t.mu, nd, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e, "info mu");
+    if (a && (e = hipMemcpy(a, p->t.a, nd, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e, "info a");
+    if (z && (e = hipMemcpy(z, p->t.z, nd, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e, "info z");
+    if (kind && (e = hipMemcpy(kind, p->t.kind, sizeof(int32_t) * p->n, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "info kind");
+    if (counts) {
+        counts[0] = p->t.ndefl;
+        counts[1] = p->t.ndirect;
+        counts[2] = p->t.width;
+        counts[3] = p->route;
+    }
+    return DCTPLUS_OK;
+}
+
+dctplus_status dctplus_plan_table(dctplus_plan_t p, const char *name, void *dst, int64_t *bytes) {
+    if (!p || !name || !bytes) return fail(DCTPLUS_EINVAL, "null argument");
+    const int64_t n = p->n, w = p->t.width, nd = p->t.ndirect;
+    struct Entry { const char *name; const void *ptr; int64_t size; };
+    const Entry tab[] = {
+        {"z", p->t.z, 8 * n}, {"zraw", p->t.zraw, 8 * n}, {"mu", p->t.mu, 8 * n}, {"a", p->t.a, 8 * n},
+        {"tau", p->t.tau, 8 * n}, {"hz", p->t.hz, 8 * n}, {"deconv", p->t.deconv, 8 * n},
+        {"rowA", p->t.rowA, 8 * n}, {"rowB", p->t.rowB, 8 * n}, {"win", p->t.win, 8 * n * w},
+        {"direct", p->t.direct, 8 * n * (nd <= kMaxDirect ? nd : 0)}, {"sintab", p->t.sintab, 8 * (2 * n + 1)},
+        {"origin", p->t.origin, 4 * n}, {"kind", p->t.kind, 4 * n}, {"ref", p->t.ref, 4 * n},
+        {"m0", p->t.m0, 4 * n}, {"rowOfBin", p->t.rowOfBin, 4 * n}, {"rowOfK", p->t.rowOfK, 4 * n},
+        {"direct_row", p->t.direct_row, 4 * (nd < kMaxDirect ? nd : kMaxDirect)},
+    };
+    for (const Entry &e : tab) {
+        if (strcmp(e.name, name) != 0) continue;
+        const int64_t cap = *bytes;
+        *bytes = e.size;
+        if (!dst || e.size == 0) return DCTPLUS_OK;
+        if (cap < e.size) return fail(DCTPLUS_EINVAL, "buffer of %lld bytes is smaller than %lld", (long long)cap,
+                                      (long long)e.size);
+        dctplus_status st = set_device(p);
+        if (st != DCTPLUS_OK) return st;
+        hipError_t err = hipMemcpy(dst, e.ptr, (size_t)e.size, hipMemcpyDeviceToHost);
+        if (err != hipSuccess) return hip_fail(err, "plan table copy");
+        return DCTPLUS_OK;
+    }
+    return fail(DCTPLUS_EINVAL, "unknown table '%s'", name);
+}
+
+void dctplus_plan_destroy(dctplus_plan_t p) {
+    if (!p) return;
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != p->device) (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    if (p->t.direct) (void)hipFree(p->t.direct);
+    if (p->t.mt32) (void)hipFree(p->t.mt32);
+    if (p->t.mt16) (void)hipFree(p->t.mt16);
+    if (p->work) (void)hipFree(p->work);
+    if (p->dev_mem) (void)hipFree(p->dev_mem);
+    if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);
+    delete p;
+}
+
+const char *dctplus_status_string(dctplus_status s) {
+    switch (s) {
+        case DCTPLUS_OK: return "ok";
+        case DCTPLUS_EINVAL: return "invalid argument";
+        case DCTPLUS_ENOMEM: return "out of memory";
+        case DCTPLUS_EDEVICE: return "device error";
+        case DCTPLUS_EUNSUPPORTED: return "unsupported";
+        case DCTPLUS_ENOCONV: return "secular solver did not converge";
+    }
+    return "unknown status";
+}
+
+const char *dctplus_last_error(void) { return g_err; }
+
+}  // extern "C"

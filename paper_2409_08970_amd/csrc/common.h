@@ -1,0 +1,88 @@
+// Internal declarations shared by the dctplus HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dctplus.h"
+
+namespace dctplus {
+
+constexpr int kMaxLogN = 14;            // n <= 16384
+constexpr int kMaxDirect = 512;         // rows summed exactly on the FAST route
+constexpr int kMaxWidth = 16;           // NUFFT window taps
+
+template <typename T>
+struct cplx {
+    T re, im;
+};
+
+// Row kinds of the output ordering.
+enum RowKind : int32_t { ROW_NUFFT = 0, ROW_DEFLATED = 1, ROW_DIRECT = 2 };
+
+// Device-side tables of a plan (all pointers into one device allocation).
+struct PlanTables {
+    int n, logn;
+    double rho;
+    // spectrum and rows
+    double *z;          // [n]    U^T v after deflation
+    double *zraw;       // [n]    U^T v before deflation
+    double *mu;         // [n]    eigenvalues in row order
+    double *a;          // [n]    column normalisers in row order (1 for deflated rows)
+    int32_t *origin;    // [n]    nearer pole (or deflated index) per row
+    double *tau;        // [n]    mu - lambda_origin per row
+    int32_t *kind;      // [n]    RowKind per row
+    int32_t *ref;       // [n]    bin (NUFFT), index k (deflated) or slot (direct)
+    // FAST route
+    double *hz;         // [n]    (-1)^(j+1) z_j / sin(pi j / n), hz_0 = 0
+    double *deconv;     // [n]    1 / window transform at frequency l
+    double *rowA;       // [n]    per bin: -a / (2 sin(n psi))
+    double *rowB;       // [n]    per bin: a z_0 / mu
+    int32_t *m0;        // [n]    per bin: first grid tap
+    double *win;        // [n * width] per bin window weights (0 for empty bins)
+    double *direct;     // [ndirect * n] exact rows a_i z_j / (mu_i - lambda_j)
+    int32_t *direct_row;// [ndirect] output row of each direct slot
+    int32_t *rowOfBin;  // [n]    output row of the NUFFT root in bin b, or -1
+    int32_t *rowOfK;    // [n]    output row of deflated index k, or -1
+    cplx<double> *tw64; // [4n]   exp(-2 pi i k / 4n)
+    cplx<float> *tw32;  // [4n]
+    double *sintab;     // [2n+1] sin(pi k / 2n)
+    // DENSE / GFT routes
+    float *mt32;        // [n * n] column-major M (M^T row-major) or X^T for GFT
+    uint16_t *mt16;     // [n * n] BF16 copy
+    int32_t *status;    // [4]    plan-build status words
+    int ndirect, ndefl, width, nj;
+};
+
+}  // namespace dctplus
+
+struct dctplus_plan_s {
+    int64_t n;
+    int logn;
+    double rho;
+    int dtype, route, device;
+    double defl_tol, direct_kappa;
+    int width;
+    void *dev_mem;            // one allocation holding every table
+    size_t dev_bytes;
+    void *work;               // lazily grown workspace (FFT scratch for large n, gradient)
+    size_t work_bytes;
+    dctplus::PlanTables t;
+};
+
+namespace dctplus {
+// thread-local error message helpers (capi.hip)
+dctplus_status fail(dctplus_status s, const char *fmt, ...);
+dctplus_status hip_fail(hipError_t e, const char *what);
+
+// route launchers (fast.hip, dense.hip, grad.hip)
+dctplus_status fast_apply(dctplus_plan_s *p, const void *in, void *out, int64_t batch, bool adjoint,
+                          hipStream_t s);
+dctplus_status dense_apply(dctplus_plan_s *p, const void *in, void *out, int64_t batch, bool adjoint,
+                           hipStream_t s);
+dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s);
+dctplus_status grad_apply(dctplus_plan_s *p, const float *y, const float *gy, int64_t batch, float *gx,
+                          double *grho, double *gv, hipStream_t s);
+dctplus_status plan_build(dctplus_plan_s *p, const double *v_host, hipStream_t s);
+dctplus_status ensure_work(dctplus_plan_s *p, size_t bytes);
+}  // namespace dctplus

@@ -1,0 +1,509 @@
+// DENSE and GFT routes on MFMA.
+//
+// DENSE (Thm 3.1 as a progressive factorisation): s_d = DCT-II(x) in LDS,
+// then y = P s_d with P = M = diag(a) C(mu, lambda) diag(z) (deflated rows
+// are unit rows).  GFT (the paper's naive matrix-vector product, the
+// comparator): y = P x with P = X^T.  Both build P once per plan in FP64 and
+// store it rounded to FP32 (and BF16).  The adjoints multiply by P^T (then a
+// DCT-III for DENSE).
+//
+// Products run on v_mfma_f32_16x16x4_f32 (FP32) or v_mfma_f32_16x16x32_bf16
+// (BF16 operands, FP32 accumulation) with signals along the MFMA M dimension:
+// 64-signal chunks are loaded coalesced into LDS, transformed there, and each
+// wave multiplies 16 of them by P, whose B fragments stay in VGPRs for the
+// whole persistent loop.  For n >= 128 a tiled GEMM with P staged through LDS
+// is used, with the DCT as a separate pass.
+#include "fft.h"
+
+namespace dctplus {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    // round to nearest even (finite inputs)
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ __bf16 bits2bf(uint16_t b) {
+    __bf16 r;
+    __builtin_memcpy(&r, &b, 2);
+    return r;
+}
+
+// P rows in FP64 -> optional DCT-III along the row (GFT) -> FP32 / BF16.
+// One workgroup per row; LDS: n doubles + n/2 complex doubles.
+__global__ void __launch_bounds__(256) k_dense_rows(PlanTables t, int gft, float *__restrict__ P32,
+                                                    uint16_t *__restrict__ P16) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = t.n, logn = t.logn, i = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
+    double *row = reinterpret_cast<double *>(smem);
+    cplx<double> *Z = reinterpret_cast<cplx<double> *>(row + n);
+    const int kind = t.kind[i];
+    const int o = t.origin[i];
+    const double tau = t.tau[i], a = t.a[i];
+    for (int j = tid; j < n; j += nthr) {
+        double v;
+        if (kind == ROW_DEFLATED) {
+            v = (j == o) ? 1.0 : 0.0;
+        } else {
+            const double zj = t.z[j];
+            const double sj = (j - o) >= 0 ? t.sintab[j - o] : -t.sintab[o - j];
+            const double d = 4.0 * sj * t.sintab[j + o];   // lambda_j - lambda_o
+            v = (zj != 0.0) ? a * zj / (tau - d) : 0.0;
+        }
+        row[j] = v;
+    }
+    __syncthreads();
+    if (gft) {
+        // row i of X^T = (U m_i)^T: inverse orthonormal DCT of the row of M
+        const int logT = logn + 2;
+        for (int k = tid; k < n / 2; k += nthr) {
+            auto get = [&](int kk) -> double { return row[kk]; };
+            Z[k] = dct3_pack<double>(get, k, logn, t.tw64, logT);
+        }
+        __syncthreads();
+        const RadixPlan rp = radix_plan(logn - 1, 1, nthr);
+        fft_dif(Z, 1, n / 2, logn - 1, t.tw64, logT, rp);
+        for (int j = tid; j < n; j += nthr) {
+            const double v = dct3_sample(Z, j, logn, rp);
+            P32[(size_t)i * n + j] = (float)v;
+            if (P16) P16[(size_t)i * n + j] = f2bf((float)v);
+        }
+    } else {
+        for (int j = tid; j < n; j += nthr) {
+            P32[(size_t)i * n + j] = (float)row[j];
+            if (P16) P16[(size_t)i * n + j] = f2bf((float)row[j]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Small n (16 <= N <= 64): persistent chunks of 64 signals.
+// ---------------------------------------------------------------------------
+constexpr int kChunk = 64;
+
+template <int N>
+struct SmallLds {
+    static constexpr int kPad = N + 1;              // row stride of the signal tile (floats)
+    static constexpr int kTile = kChunk * kPad;     // floats
+    static constexpr int kFft = kChunk * (N / 2);   // complex floats for the DCT
+    static constexpr size_t bytes = sizeof(float) * kTile + sizeof(cplx<float>) * kFft;
+};
+
+// DCT-II (dir = 0) or DCT-III (dir = 1) of the 64 rows of the LDS tile, in place.
+template <int N>
+__device__ __forceinline__ void tile_dct(float *xs, cplx<float> *Z, const cplx<float> *__restrict__ tw, int dir) {
+    constexpr int M = N / 2;
+    constexpr int logN = (N == 16) ? 4 : (N == 32) ? 5 : 6;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int logT = logN + 2;
+    const RadixPlan rp = radix_plan(logN - 1, kChunk, nthr);
+    if (dir == 0) {
+        for (int g = tid; g < kChunk * M; g += nthr) {
+            const int s = g / M, m = g % M;
+            Z[s * M + m] = dct2_pack<float>(xs + s * SmallLds<N>::kPad, m, N);
+        }
+        __syncthreads();
+        fft_dif(Z, kChunk, M, logN - 1, tw, logT, rp);
+        for (int g = tid; g < kChunk * (M + 1); g += nthr) {
+            const int s = g / (M + 1), k = g % (M + 1);
+            float Xk, XNk;
+            dct2_post(Z + s * M, k, logN, rp, tw, logT, Xk, XNk);
+            xs[s * SmallLds<N>::kPad + k] = Xk;
+            if (k > 0 && k < M) xs[s * SmallLds<N>::kPad + N - k] = XNk;
+        }
+    } else {
+        for (int g = tid; g < kChunk * M; g += nthr) {
+            const int s = g / M, k = g % M;
+            const float *row = xs + s * SmallLds<N>::kPad;
+            auto get = [&](int kk) -> float { return row[kk]; };
+            Z[s * M + k] = dct3_pack<float>(get, k, logN, tw, logT);
+        }
+        __syncthreads();
+        fft_dif(Z, kChunk, M, logN - 1, tw, logT, rp);
+        for (int g = tid; g < kChunk * N; g += nthr) {
+            const int s = g / N, j = g % N;
+            xs[s * SmallLds<N>::kPad + j] = dct3_sample(Z + s * M, j, logN, rp);
+        }
+    }
+    __syncthreads();
+}
+
+// Forward (adj = 0): y = P s with s = DCT(x) (pre_dct) or x.
+// Adjoint (adj = 1): x = DCT-III(P^T y) (pre_dct) or P^T y.
+template <int N, bool BF16>
+__global__ void __launch_bounds__(256) k_dense_small(const float *__restrict__ in, float *__restrict__ out,
+                                                     int64_t batch, const float *__restrict__ P32,
+                                                     const uint16_t *__restrict__ P16,
+                                                     const cplx<float> *__restrict__ tw, int adj, int pre_dct) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *xs = reinterpret_cast<float *>(smem);
+    cplx<float> *Z = reinterpret_cast<cplx<float> *>(xs + SmallLds<N>::kTile);
+    constexpr int kPad = SmallLds<N>::kPad;
+    constexpr int NT = N / 16;                       // output column tiles
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int64_t nchunks = (batch + kChunk - 1) / kChunk;
+
+    // B fragments of B = P^T (forward: B[k][j] = P[j][k]) or B = P (adjoint)
+    constexpr int KS = BF16 ? N / 32 : N / 4;        // k-steps
+    constexpr int KSr = KS > 0 ? KS : 1;
+    float bf32[BF16 ? 1 : KSr * NT];
+    bf8 bfb[BF16 ? KSr * NT : 1];
+    if constexpr (!BF16) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int k = 4 * s + lq, j = 16 * t + l16;
+                bf32[s * NT + t] = adj ? P32[(size_t)k * N + j] : P32[(size_t)j * N + k];
+            }
+    } else {
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                bf8 v;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int k = 32 * s + 8 * lq + e, j = 16 * t + l16;
+                    v[e] = bits2bf(adj ? P16[(size_t)k * N + j] : P16[(size_t)j * N + k]);
+                }
+                bfb[s * NT + t] = v;
+            }
+    }
+
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int64_t sig0 = c * kChunk;
+        const int nvalid = (int)((batch - sig0) < kChunk ? (batch - sig0) : kChunk);
+        // coalesced load of the chunk (rows beyond the batch are zero)
+        for (int g = tid; g < kChunk * N; g += blockDim.x) {
+            const int s = g / N, j = g % N;
+            xs[s * kPad + j] = (s < nvalid) ? in[(sig0 + s) * N + j] : 0.0f;
+        }
+        __syncthreads();
+        if (pre_dct && !adj) tile_dct<N>(xs, Z, tw, 0);
+
+        // this wave's 16 signals times B
+        f4 acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+        const float *arow = xs + (16 * wave + l16) * kPad;
+        if constexpr (!BF16) {
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const float av = arow[4 * s + lq];
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bf32[s * NT + t], acc[t], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                bf8 av;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) av[e] = bits2bf(f2bf(arow[32 * s + 8 * lq + e]));
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bfb[s * NT + t], acc[t], 0, 0, 0);
+            }
+        }
+        if (adj && pre_dct) {
+            // stage P^T y in the tile (this wave's own rows), then DCT-III
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) xs[(16 * wave + 4 * lq + v) * kPad + 16 * t + l16] = acc[t][v];
+            __syncthreads();
+            tile_dct<N>(xs, Z, tw, 1);
+            for (int g = tid; g < kChunk * N; g += blockDim.x) {
+                const int s = g / N, j = g % N;
+                if (s < nvalid) out[(sig0 + s) * N + j] = xs[s * kPad + j];
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int s = 16 * wave + 4 * lq + v;
+                    if (s < nvalid) out[(sig0 + s) * N + 16 * t + l16] = acc[t][v];
+                }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tiny n (4, 8): one thread per signal, P and the DCT matrix from LDS.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(256) k_dense_tiny(const float *__restrict__ in, float *__restrict__ out, int64_t batch,
+                             const float *__restrict__ P32, const cplx<float> *__restrict__ tw, int adj,
+                             int pre_dct) {
+    __shared__ float Ps[N * N], Us[N * N];
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        Ps[e] = P32[e];
+        const int j = e / N, k = e % N;   // U[j][k] = c_k cos(pi k (2j+1) / 2N) = Re tw4N^(k(2j+1))
+        const float ck = (k == 0) ? sqrtf(1.0f / N) : sqrtf(2.0f / N);
+        Us[e] = ck * tw[(k * (2 * j + 1)) % (4 * N)].re;
+    }
+    __syncthreads();
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < batch; b += (int64_t)gridDim.x * blockDim.x) {
+        float v[N], w[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) v[j] = in[b * N + j];
+        if (!adj) {
+            if (pre_dct) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    float a = 0.f;
+#pragma unroll
+                    for (int j = 0; j < N; ++j) a += Us[j * N + k] * v[j];
+                    w[k] = a;
+                }
+#pragma unroll
+                for (int k = 0; k < N; ++k) v[k] = w[k];
+            }
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                float a = 0.f;
+#pragma unroll
+                for (int k = 0; k < N; ++k) a += Ps[i * N + k] * v[k];
+                w[i] = a;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                float a = 0.f;
+#pragma unroll
+                for (int i = 0; i < N; ++i) a += Ps[i * N + k] * v[i];
+                w[k] = a;
+            }
+            if (pre_dct) {
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    float a = 0.f;
+#pragma unroll
+                    for (int k = 0; k < N; ++k) a += Us[j * N + k] * w[k];
+                    v[j] = a;
+                }
+#pragma unroll
+                for (int j = 0; j < N; ++j) w[j] = v[j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) out[b * N + j] = w[j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Large n: batched DCT pass + tiled MFMA GEMM  C[b][j] = sum_k A[b][k] B[k][j],
+// with B = P^T (forward) or P (adjoint).  Tile 64 signals x 64 outputs, K step 16.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_dct_rows(PlanTables t, const float *__restrict__ in, float *__restrict__ out,
+                                                  int64_t batch, int dir, int nsig) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = t.n, logn = t.logn, tid = threadIdx.x, nthr = blockDim.x;
+    const int logT = logn + 2, M = n / 2;
+    cplx<float> *Z = reinterpret_cast<cplx<float> *>(smem);
+    const int64_t s0 = (int64_t)blockIdx.x * nsig;
+    const int ns = (int)((batch - s0) < nsig ? (batch - s0) : nsig);
+    const RadixPlan rp = radix_plan(logn - 1, ns, nthr);
+    if (dir == 0) {
+        for (int g = tid; g < ns * M; g += nthr) {
+            const int s = g / M, m = g % M;
+            Z[(size_t)s * M + m] = dct2_pack<float>(in + (s0 + s) * n, m, n);
+        }
+        __syncthreads();
+        fft_dif(Z, ns, M, logn - 1, t.tw32, logT, rp);
+        for (int g = tid; g < ns * (M + 1); g += nthr) {
+            const int s = g / (M + 1), k = g % (M + 1);
+            float Xk, XNk;
+            dct2_post(Z + (size_t)s * M, k, logn, rp, t.tw32, logT, Xk, XNk);
+            out[(s0 + s) * n + k] = Xk;
+            if (k > 0 && k < M) out[(s0 + s) * n + n - k] = XNk;
+        }
+    } else {
+        for (int g = tid; g < ns * M; g += nthr) {
+            const int s = g / M, k = g % M;
+            const float *row = in + (s0 + s) * n;
+            auto get = [&](int kk) -> float { return row[kk]; };
+            Z[(size_t)s * M + k] = dct3_pack<float>(get, k, logn, t.tw32, logT);
+        }
+        __syncthreads();
+        fft_dif(Z, ns, M, logn - 1, t.tw32, logT, rp);
+        for (int g = tid; g < ns * n; g += nthr) {
+            const int s = g / n, j = g % n;
+            out[(s0 + s) * n + j] = dct3_sample(Z + (size_t)s * M, j, logn, rp);
+        }
+    }
+}
+
+constexpr int TBM = 64, TBN = 64, TBK = 16;
+
+__global__ void __launch_bounds__(256) k_gemm(const float *__restrict__ A, const float *__restrict__ P,
+                                              float *__restrict__ C, int64_t batch, int n, int transB) {
+    // B[k][j] = transB ? P[j][k] : P[k][j]
+    __shared__ float As[TBM][TBK + 1];
+    __shared__ float Bs[TBK][TBN + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int64_t m0 = (int64_t)blockIdx.y * TBM;
+    const int n0 = blockIdx.x * TBN;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;   // 2x2 waves, 32x32 each
+    f4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < n; k0 += TBK) {
+        for (int e = tid; e < TBM * TBK; e += 256) {
+            const int r = e / TBK, k = e % TBK;
+            const int64_t row = m0 + r;
+            As[r][k] = row < batch ? A[row * n + k0 + k] : 0.0f;
+        }
+        for (int e = tid; e < TBK * TBN; e += 256) {
+            int k, j;
+            if (transB) { j = e / TBK; k = e % TBK; }
+            else { k = e / TBN; j = e % TBN; }
+            Bs[k][j] = transB ? P[(size_t)(n0 + j) * n + k0 + k] : P[(size_t)(k0 + k) * n + n0 + j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < TBK / 4; ++s) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const float av = As[wm + 16 * a + l16][4 * s + lq];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const float bv = Bs[4 * s + lq][wn + 16 * b + l16];
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[a][b], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = m0 + wm + 16 * a + 4 * lq + v;
+                if (row < batch) C[row * n + n0 + wn + 16 * b + l16] = acc[a][b][v];
+            }
+}
+
+int persistent_blocks(int64_t nchunks) {
+    static int ncu = 0;
+    if (ncu == 0) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+        if (ncu <= 0) ncu = 256;
+    }
+    const int64_t cap = (int64_t)ncu * 4;
+    return (int)(nchunks < cap ? nchunks : cap);
+}
+
+template <int N, bool BF>
+void launch_small(const dctplus_plan_s *p, const float *in, float *out, int64_t batch, int adj, int pre,
+                  hipStream_t s) {
+    const int64_t nchunks = (batch + kChunk - 1) / kChunk;
+    const int blocks = persistent_blocks(nchunks);
+    hipLaunchKernelGGL((k_dense_small<N, BF>), dim3(blocks), dim3(256), SmallLds<N>::bytes, s, in, out, batch,
+                       (const float *)p->t.mt32, (const uint16_t *)p->t.mt16, (const cplx<float> *)p->t.tw32, adj,
+                       pre);
+}
+
+}  // namespace
+
+dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s) {
+    const int n = (int)p->n;
+    const size_t elems = (size_t)n * n;
+    hipError_t e = hipMalloc(&p->t.mt32, sizeof(float) * elems);
+    if (e != hipSuccess) {
+        p->t.mt32 = nullptr;
+        (void)hipGetLastError();
+        return fail(DCTPLUS_ENOMEM, "hipMalloc for the %d x %d dense factor failed", n, n);
+    }
+    if (p->dtype == DCTPLUS_BF16) {
+        e = hipMalloc(&p->t.mt16, sizeof(uint16_t) * elems);
+        if (e != hipSuccess) {
+            p->t.mt16 = nullptr;
+            (void)hipGetLastError();
+            return fail(DCTPLUS_ENOMEM, "hipMalloc for the BF16 dense factor failed");
+        }
+    }
+    const int gft = (p->route == DCTPLUS_ROUTE_GFT);
+    const size_t lds = sizeof(double) * n + sizeof(cplx<double>) * (n / 2);
+    hipLaunchKernelGGL(k_dense_rows, dim3(n), dim3(256), lds, s, p->t, gft, p->t.mt32, p->t.mt16);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "dense factor build");
+    return DCTPLUS_OK;
+}
+
+dctplus_status dense_apply(dctplus_plan_s *p, const void *inv, void *outv, int64_t batch, bool adjoint,
+                           hipStream_t s) {
+    const int n = (int)p->n;
+    const float *in = (const float *)inv;
+    float *out = (float *)outv;
+    const int pre = (p->route == DCTPLUS_ROUTE_DENSE);
+    const int adj = adjoint ? 1 : 0;
+    const bool bf = (p->dtype == DCTPLUS_BF16);
+    if (n <= 8) {
+        const int64_t blocks64 = (batch + 255) / 256;
+        const int blocks = (int)(blocks64 < 4096 ? blocks64 : 4096);
+        if (n == 4)
+            hipLaunchKernelGGL((k_dense_tiny<4>), dim3(blocks), dim3(256), 0, s, in, out, batch, p->t.mt32,
+                               p->t.tw32, adj, pre);
+        else
+            hipLaunchKernelGGL((k_dense_tiny<8>), dim3(blocks), dim3(256), 0, s, in, out, batch, p->t.mt32,
+                               p->t.tw32, adj, pre);
+    } else if (n <= 64) {
+        if (!bf) {
+            if (n == 16) launch_small<16, false>(p, in, out, batch, adj, pre, s);
+            else if (n == 32) launch_small<32, false>(p, in, out, batch, adj, pre, s);
+            else launch_small<64, false>(p, in, out, batch, adj, pre, s);
+        } else {
+            if (n == 16) return fail(DCTPLUS_EUNSUPPORTED, "BF16 dense route needs n >= 32");
+            if (n == 32) launch_small<32, true>(p, in, out, batch, adj, pre, s);
+            else launch_small<64, true>(p, in, out, batch, adj, pre, s);
+        }
+    } else {
+        if (bf) return fail(DCTPLUS_EUNSUPPORTED, "BF16 dense route supports n <= 64");
+        float *tmp = nullptr;
+        if (pre) {
+            dctplus_status st = ensure_work(p, sizeof(float) * (size_t)batch * n);
+            if (st != DCTPLUS_OK) return st;
+            tmp = (float *)p->work;
+        }
+        const int nsig = n >= 4096 ? 1 : 4096 / n;
+        const size_t lds = sizeof(cplx<float>) * (size_t)nsig * (n / 2);
+        const dim3 dgrid((unsigned)((batch + nsig - 1) / nsig));
+        const dim3 ggrid(n / TBN, (unsigned)((batch + TBM - 1) / TBM));
+        if (!adjoint) {
+            const float *A = in;
+            if (pre) {
+                hipLaunchKernelGGL(k_dct_rows, dgrid, dim3(256), lds, s, p->t, in, tmp, batch, 0, nsig);
+                A = tmp;
+            }
+            hipLaunchKernelGGL(k_gemm, ggrid, dim3(256), 0, s, A, (const float *)p->t.mt32, out, batch, n, 1);
+        } else {
+            float *C = pre ? tmp : out;
+            hipLaunchKernelGGL(k_gemm, ggrid, dim3(256), 0, s, in, (const float *)p->t.mt32, C, batch, n, 0);
+            if (pre) hipLaunchKernelGGL(k_dct_rows, dgrid, dim3(256), lds, s, p->t, tmp, out, batch, 1, nsig);
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "dense route launch");
+    return DCTPLUS_OK;
+}
+
+}  // namespace dctplus

@@ -1,0 +1,263 @@
+// Workgroup-cooperative complex FFT for gfx950, plus the complex helpers the
+// real transforms (DCT-II/III, DST-I) are built from.
+//
+// The FFT is an in-place decimation-in-frequency transform made of radix-2^r
+// passes (r <= 4).  Each pass gives every thread whole R-point butterflies
+// held in registers; passes are separated by workgroup barriers.  The output
+// is left in digit-reversed order; dif_pos() maps a frequency index to its
+// slot, and the consumers of an FFT read through it instead of paying for a
+// reordering pass.  Several independent signals (nsig, `stride` complex
+// elements apart) are transformed by one call.  The buffer may live in LDS or
+// in global scratch: the code only uses generic pointers and barriers.
+#pragma once
+
+#include "common.h"
+
+namespace dctplus {
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return {a.re, -a.im}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return {a.re * s, a.im * s}; }
+// a / (2i) = (a.im / 2, -a.re / 2)
+template <typename T>
+__device__ __forceinline__ cplx<T> cdiv2i(cplx<T> a) { return {a.im * T(0.5), -a.re * T(0.5)}; }
+
+// exp(-2 pi i q / 16), q = 0..7 (the only in-register twiddles a radix-16
+// butterfly needs).
+__device__ constexpr double kW16re[8] = {1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508977,
+                                         0.0, -0.38268343236508977, -0.70710678118654752, -0.92387953251128674};
+__device__ constexpr double kW16im[8] = {0.0, -0.38268343236508977, -0.70710678118654752, -0.92387953251128674,
+                                         -1.0, -0.92387953251128674, -0.70710678118654752, -0.38268343236508977};
+
+template <int LR>
+__device__ __forceinline__ constexpr int bitrev(int k) {
+    int r = 0;
+    for (int i = 0; i < LR; ++i) r |= ((k >> i) & 1) << (LR - 1 - i);
+    return r;
+}
+
+// R-point DFT (R = 2^LR <= 16) in registers, natural order in and out.
+template <int LR, typename T>
+__device__ __forceinline__ void dft_reg(cplx<T> *x) {
+    constexpr int R = 1 << LR;
+#pragma unroll
+    for (int s = 0; s < LR; ++s) {
+        const int half = R >> (s + 1);
+#pragma unroll
+        for (int blk = 0; blk < R; blk += 2 * half) {
+#pragma unroll
+            for (int j = 0; j < half; ++j) {
+                cplx<T> a = x[blk + j], b = x[blk + j + half];
+                x[blk + j] = cadd(a, b);
+                cplx<T> d = csub(a, b);
+                const int q = j * (16 / (2 * half));     // twiddle exp(-2 pi i j / 2half) in 1/16 units
+                if (q == 0) {
+                    x[blk + j + half] = d;
+                } else if (q == 4) {                        // multiply by -i
+                    x[blk + j + half] = {d.im, -d.re};
+                } else {
+                    cplx<T> w = {T(kW16re[q]), T(kW16im[q])};
+                    x[blk + j + half] = cmul(d, w);
+                }
+            }
+        }
+    }
+    cplx<T> y[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) y[k] = x[bitrev<LR>(k)];
+#pragma unroll
+    for (int k = 0; k < R; ++k) x[k] = y[k];
+}
+
+// Sequence of pass radices for an N = 2^logN transform of nsig signals on
+// nthreads threads: radix 16 while every thread still gets a butterfly,
+// smaller radices otherwise.  Must be computed identically by the FFT and by
+// whoever reads its output.
+struct RadixPlan {
+    int np;          // number of passes
+    uint32_t code;   // 2 bits per pass: log2(radix) - 1
+    __device__ __forceinline__ int lr(int i) const { return (int)((code >> (2 * i)) & 3u) + 1; }
+};
+
+__device__ __forceinline__ RadixPlan radix_plan(int logN, int nsig, int nthreads) {
+    RadixPlan rp;
+    rp.np = 0;
+    rp.code = 0;
+    int rem = logN;
+    while (rem > 0) {
+        int lr = rem < 4 ? rem : 4;
+        while (lr > 1 && (nsig << (logN - lr)) < nthreads) --lr;
+        rp.code |= (uint32_t)(lr - 1) << (2 * rp.np);
+        ++rp.np;
+        rem -= lr;
+    }
+    return rp;
+}
+
+// Slot of frequency k in the digit-reversed output.
+__device__ __forceinline__ int dif_pos(int k, const RadixPlan &rp, int logN) {
+    int p = 0, logL = logN;
+    uint32_t code = rp.code;
+    for (int i = 0; i < rp.np; ++i) {
+        const int lr = (int)(code & 3u) + 1;
+        code >>= 2;
+        const int k2 = k & ((1 << lr) - 1);
+        k >>= lr;
+        logL -= lr;
+        p += k2 << logL;
+    }
+    return p;
+}
+
+template <int LR, typename T>
+__device__ __forceinline__ void fft_pass(cplx<T> *buf, int nsig, int stride, int logN, int logL,
+                                         const cplx<T> *__restrict__ tw, int logNtw, int tid, int nthr) {
+    constexpr int R = 1 << LR;
+    const int logm = logL - LR;
+    const int m = 1 << logm;
+    const int lg = logN - LR;                 // log2(groups per signal)
+    const int total = nsig << lg;
+    for (int g = tid; g < total; g += nthr) {
+        const int s = g >> lg;
+        const int rem = g & ((1 << lg) - 1);
+        const int sub = rem >> logm;
+        const int j = rem & (m - 1);
+        cplx<T> *base = buf + (size_t)s * stride + (sub << logL) + j;
+        cplx<T> x[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r] = base[r << logm];
+        dft_reg<LR>(x);
+        if (logm > 0) {
+            const int sh = logNtw - logL;
+#pragma unroll
+            for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[(j * r) << sh]);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) base[r << logm] = x[r];
+    }
+}
+
+// In-place forward FFT (exp(-2 pi i j k / N)).  The caller must barrier
+// before (input written) and may read the output right after return.
+template <typename T>
+__device__ __forceinline__ void fft_dif(cplx<T> *buf, int nsig, int stride, int logN, const cplx<T> *__restrict__ tw,
+                        int logNtw, const RadixPlan &rp) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    int logL = logN;
+    for (int i = 0; i < rp.np; ++i) {
+        const int lr = rp.lr(i);
+        switch (lr) {
+            case 1: fft_pass<1, T>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
+            case 2: fft_pass<2, T>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
+            case 3: fft_pass<3, T>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
+            default: fft_pass<4, T>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
+        }
+        logL -= lr;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Real transforms on top of the complex FFT (per signal, N = 2^logN real
+// points).  Twiddle tables hold exp(-2 pi i k / Ntw) with Ntw >= 4N.
+// ---------------------------------------------------------------------------
+
+// Makhoul reordering for the DCT-II: v_q = x_{2q} (q < N/2), v_{N-1-q} = x_{2q+1};
+// packed complex input Z_m = v_{2m} + i v_{2m+1}, m < N/2.  Returns Z_m.
+template <typename T, typename Src>
+__device__ __forceinline__ cplx<T> dct2_pack(const Src *x, int m, int N) {
+    auto vq = [&](int q) -> T { return q < N / 2 ? T(x[2 * q]) : T(x[2 * (N - 1 - q) + 1]); };
+    return {vq(2 * m), vq(2 * m + 1)};
+}
+
+// Orthonormal DCT-II outputs X_k and X_{N-k} (0 <= k <= N/2) from the FFT of
+// the packed sequence (M = N/2 points, digit-reversed per rp).  For k = 0 the
+// second output is meaningless; for k = N/2 both are X_{N/2}.
+template <typename T>
+__device__ __forceinline__ void dct2_post(const cplx<T> *Zh, int k, int logN, const RadixPlan &rp,
+                                          const cplx<T> *__restrict__ tw, int logNtw, T &Xk, T &XNk) {
+    const int N = 1 << logN, M = N >> 1, logM = logN - 1;
+    const cplx<T> a = Zh[dif_pos(k & (M - 1), rp, logM)];
+    const cplx<T> b = cconj(Zh[dif_pos((M - k) & (M - 1), rp, logM)]);
+    const cplx<T> E = cscale(cadd(a, b), T(0.5));
+    const cplx<T> O = cdiv2i(csub(a, b));
+    const cplx<T> wN = tw[(k << (logNtw - logN)) & ((1 << logNtw) - 1)];
+    const cplx<T> V = cadd(E, cmul(wN, O));
+    const cplx<T> w4 = tw[k << (logNtw - logN - 2)];
+    const cplx<T> P = cmul(w4, V);
+    const T c0 = T(1) / sqrt(T(N)), c1 = sqrt(T(2) / T(N));
+    Xk = P.re * (k == 0 ? c0 : c1);
+    XNk = -P.im * c1;
+}
+
+// Inverse of the above: for 0 <= k < M = N/2, the FFT input Zh_k (natural order,
+// conjugated so that a forward FFT performs the inverse) built from the
+// orthonormal coefficients X (X_k read through get(k)).
+template <typename T, typename Get>
+__device__ __forceinline__ cplx<T> dct3_pack(Get get, int k, int logN, const cplx<T> *__restrict__ tw,
+                                             int logNtw) {
+    const int N = 1 << logN, M = N >> 1;
+    const T c0 = sqrt(T(N)), c1 = sqrt(T(N) / T(2));   // 1 / c_k
+    auto V = [&](int kk) -> cplx<T> {
+        // V_kk = exp(+i pi kk / 2N) (X'_kk - i X'_{N-kk}),  X' = X / c
+        const T xr = get(kk) * (kk == 0 ? c0 : c1);
+        const T xi = kk == 0 ? T(0) : get(N - kk) * c1;
+        const cplx<T> w = cconj(tw[kk << (logNtw - logN - 2)]);
+        return cmul(w, cplx<T>{xr, -xi});
+    };
+    const cplx<T> Vk = V(k);
+    const cplx<T> Vm = cconj(V(M - k));
+    const cplx<T> E = cscale(cadd(Vk, Vm), T(0.5));
+    const cplx<T> winv = cconj(tw[(k << (logNtw - logN)) & ((1 << logNtw) - 1)]);
+    const cplx<T> O = cmul(cscale(csub(Vk, Vm), T(0.5)), winv);
+    const cplx<T> Z = {E.re - O.im, E.im + O.re};     // E + i O
+    return cconj(Z);
+}
+
+// Output sample q of the inverse DCT: x_{2q} = v_q (q < N/2), x_{2(N-1-q)+1} = v_q,
+// where v_{2m} + i v_{2m+1} = conj(FFT(conj Zh))_m / M.  Returns x_j.
+template <typename T>
+__device__ __forceinline__ T dct3_sample(const cplx<T> *Zf, int j, int logN, const RadixPlan &rp) {
+    const int N = 1 << logN, M = N >> 1, logM = logN - 1;
+    const int q = (j & 1) ? (N - 1 - (j >> 1)) : (j >> 1);
+    const cplx<T> z = Zf[dif_pos(q >> 1, rp, logM)];
+    // conj(z) / M: real part for even q, imaginary part (of the conjugate) for odd q
+    return (q & 1) ? (-z.im / T(M)) : (z.re / T(M));
+}
+
+// DST-I of length Nn-1 (c_l = 2 sum_{j=1}^{Nn-1} h_j sin(pi j l / Nn)) through
+// the FFT of the odd extension u (length 2 Nn) packed into Nn complex points.
+// Output c_l for 1 <= l < Nn from the digit-reversed FFT Zh.
+template <typename T>
+__device__ __forceinline__ T dst1_post(const cplx<T> *Zh, int l, int logNn, const RadixPlan &rp,
+                                       const cplx<T> *__restrict__ tw, int logNtw) {
+    const int Nn = 1 << logNn;
+    const cplx<T> a = Zh[dif_pos(l, rp, logNn)];
+    const cplx<T> b = cconj(Zh[dif_pos(Nn - l, rp, logNn)]);
+    const cplx<T> E = cscale(cadd(a, b), T(0.5));
+    const cplx<T> O = cdiv2i(csub(a, b));
+    const cplx<T> w = tw[l << (logNtw - logNn - 1)];   // exp(-2 pi i l / 2Nn)
+    const cplx<T> D = cadd(E, cmul(w, O));
+    return -D.im;
+}
+
+// ---------------------------------------------------------------------------
+// Reductions
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+}  // namespace dctplus

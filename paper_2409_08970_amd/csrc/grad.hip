@@ -1,0 +1,196 @@
+// Gradient of a loss l(y), y = X^T x, with respect to x, rho and v.
+//
+// First-order perturbation of L x_i = mu_i x_i gives
+//   dx_i = sum_{k != i} x_k (x_k^T dL x_i) / (mu_i - mu_k),
+//   dL   = drho v v^T + rho (dv v^T + v dv^T).
+// With G = sum_b gy_b y_b^T (n x n), A_ik = G_ik / (mu_i - mu_k) (A_ii = 0)
+// and w = X^T v (w_i = a_i / rho for secular rows by Lemma 4.2 and the
+// secular equation; w_k = u_k^T v for deflated rows):
+//   dl/dx   = X gy                       (the adjoint transform)
+//   dl/drho = w^T A w
+//   dl/dv   = rho X (A + A^T) w
+// G is a batch reduction (K = batch) on MFMA with split-K partials summed in
+// FP64 in a fixed order (deterministic); the mu gaps and the O(n^2) tail
+// are FP64.
+#include "fft.h"
+
+namespace dctplus {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int GT = 64;      // output tile
+constexpr int GK = 16;      // batch rows per LDS stage
+
+// partial[split][i][k] = sum over this split's rows b of gy[b][i] * y[b][k]
+__global__ void __launch_bounds__(256) k_gram(const float *__restrict__ gy, const float *__restrict__ y,
+                                              float *__restrict__ partial, int64_t batch, int n, int64_t rows_per) {
+    __shared__ float As[GK][GT + 1];   // gy tile [b][i]
+    __shared__ float Bs[GK][GT + 1];   // y tile  [b][k]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int i0 = blockIdx.x * GT, k0 = blockIdx.y * GT, split = blockIdx.z;
+    const int64_t b0 = (int64_t)split * rows_per;
+    int64_t b1 = b0 + rows_per;
+    if (b1 > batch) b1 = batch;
+    const int wi = (wave >> 1) * 32, wk = (wave & 1) * 32;
+    f4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t bb = b0; bb < b1; bb += GK) {
+        for (int e = tid; e < GK * GT; e += 256) {
+            const int r = e / GT, c = e % GT;
+            const int64_t row = bb + r;
+            As[r][c] = (row < b1 && i0 + c < n) ? gy[row * n + i0 + c] : 0.0f;
+            Bs[r][c] = (row < b1 && k0 + c < n) ? y[row * n + k0 + c] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < GK / 4; ++s) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const float av = As[4 * s + lq][wi + 16 * a + l16];   // A[i][b] = gy[b][i]
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const float bv = Bs[4 * s + lq][wk + 16 * b + l16];
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[a][b], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    float *P = partial + (size_t)split * n * n;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + wi + 16 * a + 4 * lq + v, k = k0 + wk + 16 * b + l16;
+                if (i < n && k < n) P[(size_t)i * n + k] = acc[a][b][v];
+            }
+}
+
+__device__ __forceinline__ double wcoef(const PlanTables &t, int i) {
+    // w_i = x_i^T v
+    if (t.kind[i] == ROW_DEFLATED) return t.zraw[t.origin[i]];
+    return t.a[i] / t.rho;
+}
+
+// r_i = sum_k (G_ik - G_ki) / (mu_i - mu_k) w_k ,  q_i = w_i sum_k G_ik w_k / (mu_i - mu_k)
+__global__ void k_grad_vec(PlanTables t, const float *__restrict__ partial, int nsplit, double *__restrict__ rvec,
+                           double *__restrict__ qvec) {
+    const int n = t.n;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double mui = t.mu[i], wi = wcoef(t, i);
+    double r = 0.0, q = 0.0;
+    for (int k = 0; k < n; ++k) {
+        if (k == i) continue;
+        double gik = 0.0, gki = 0.0;
+        for (int sp = 0; sp < nsplit; ++sp) {
+            gik += (double)partial[(size_t)sp * n * n + (size_t)i * n + k];
+            gki += (double)partial[(size_t)sp * n * n + (size_t)k * n + i];
+        }
+        const double inv = 1.0 / (mui - t.mu[k]);
+        const double wk = wcoef(t, k);
+        r += (gik - gki) * inv * wk;
+        q += gik * inv * wk;
+    }
+    rvec[i] = r;
+    qvec[i] = q * wi;
+}
+
+// dl/drho = sum_i q_i ; dl/dv = rho X r  (FP64: Cauchy transpose, then DCT-III)
+__global__ void __launch_bounds__(256) k_grad_final(PlanTables t, const double *__restrict__ rvec,
+                                                    const double *__restrict__ qvec, double *__restrict__ grho,
+                                                    double *__restrict__ gv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = t.n, logn = t.logn, tid = threadIdx.x, nthr = blockDim.x;
+    double *sdv = reinterpret_cast<double *>(smem);
+    cplx<double> *Z = reinterpret_cast<cplx<double> *>(sdv + n);
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int i = tid; i < n; i += nthr) acc += qvec[i];
+    acc = wave_sum(acc);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    // s_j = sum_i M_ij r_i
+    for (int j = tid; j < n; j += nthr) {
+        double s = 0.0;
+        const double zj = t.z[j];
+        for (int i = 0; i < n; ++i) {
+            const int kind = t.kind[i], o = t.origin[i];
+            if (kind == ROW_DEFLATED) {
+                if (o == j) s += rvec[i];
+            } else if (zj != 0.0) {
+                const double sj = (j - o) >= 0 ? t.sintab[j - o] : -t.sintab[o - j];
+                const double d = 4.0 * sj * t.sintab[j + o];
+                s += t.a[i] * zj / (t.tau[i] - d) * rvec[i];
+            }
+        }
+        sdv[j] = s;
+    }
+    __syncthreads();
+    if (tid == 0 && grho) {
+        double s = 0.0;
+        for (int w = 0; w < nthr / 64; ++w) s += red[w];
+        *grho = s;
+    }
+    if (!gv) return;
+    const int logT = logn + 2;
+    for (int k = tid; k < n / 2; k += nthr) {
+        auto get = [&](int kk) -> double { return sdv[kk]; };
+        Z[k] = dct3_pack<double>(get, k, logn, t.tw64, logT);
+    }
+    __syncthreads();
+    const RadixPlan rp = radix_plan(logn - 1, 1, nthr);
+    fft_dif(Z, 1, n / 2, logn - 1, t.tw64, logT, rp);
+    for (int j = tid; j < n; j += nthr) gv[j] = t.rho * dct3_sample(Z, j, logn, rp);
+}
+
+}  // namespace
+
+dctplus_status grad_apply(dctplus_plan_s *p, const float *y, const float *gy, int64_t batch, float *gx,
+                          double *grho, double *gv, hipStream_t s) {
+    const int n = (int)p->n;
+    if (gx) {
+        dctplus_status st = (p->route == DCTPLUS_ROUTE_FAST) ? fast_apply(p, gy, gx, batch, true, s)
+                                                             : dense_apply(p, gy, gx, batch, true, s);
+        if (st != DCTPLUS_OK) return st;
+    }
+    if (!grho && !gv) return DCTPLUS_OK;
+    if (n > 4096) return fail(DCTPLUS_EUNSUPPORTED, "gradient with respect to rho and v supports n <= 4096");
+    // split-K so that the grid has ~512+ workgroups and the partials stay modest
+    const int nt = (n + GT - 1) / GT;
+    const int tiles = nt * nt;
+    int nsplit = 512 / tiles;
+    if (nsplit < 1) nsplit = 1;
+    if (nsplit > 64) nsplit = 64;
+    while (nsplit > 1 && (size_t)nsplit * n * n * sizeof(float) > (size_t)256 << 20) nsplit >>= 1;
+    int64_t rows_per = (batch + nsplit - 1) / nsplit;
+    rows_per = (rows_per + GK - 1) / GK * GK;
+    if (rows_per < GK) rows_per = GK;
+    const size_t pbytes = (size_t)nsplit * n * n * sizeof(float);
+    const size_t vbytes = 2 * sizeof(double) * n;
+    // the workspace may already hold a FAST/DENSE scratch from the gx call above,
+    // which has completed its use of it in stream order
+    dctplus_status st = ensure_work(p, pbytes + vbytes);
+    if (st != DCTPLUS_OK) return st;
+    float *partial = (float *)p->work;
+    double *rvec = (double *)((char *)p->work + pbytes);
+    double *qvec = rvec + n;
+    hipLaunchKernelGGL(k_gram, dim3(nt, nt, nsplit), dim3(256), 0, s, gy, y, partial, batch, n, rows_per);
+    hipLaunchKernelGGL(k_grad_vec, dim3((n + 255) / 256), dim3(256), 0, s, p->t, (const float *)partial, nsplit,
+                       rvec, qvec);
+    const size_t lds = sizeof(double) * n + sizeof(cplx<double>) * (n / 2);
+    hipLaunchKernelGGL(k_grad_final, dim3(1), dim3(256), lds, s, p->t, (const double *)rvec, (const double *)qvec,
+                       grho, gv);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "gradient launch");
+    return DCTPLUS_OK;
+}
+
+}  // namespace dctplus

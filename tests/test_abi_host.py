@@ -1,0 +1,97 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/dctplus.h, and rejects bad arguments before any device
+work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dctplus.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dctplus_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2409_08970_amd import _binding as B
+    if not os.path.exists(B.LIB_PATH):
+        from paper_2409_08970_amd import build
+        build.build()
+    return B.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("dctplus_plan", "dctplus_forward", "dctplus_adjoint", "dctplus_grad",
+                     "dctplus_plan_destroy", "dctplus_plan_info", "dctplus_status_string"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2409_08970_amd import _binding as B
+    names = _declared_functions()
+    missing = [nm for nm in names if not hasattr(lib, nm)]
+    assert not missing, missing
+    assert set(names) == set(B.EXPORTED)
+
+
+def test_status_strings_and_defaults(lib):
+    from paper_2409_08970_amd import _binding as B
+    assert B.dctplus_status_string(0) == "ok"
+    assert B.dctplus_status_string(1) == "invalid argument"
+    assert B.dctplus_status_string(99) == "unknown status"
+    o = B.dctplus_default_opts()
+    assert (o.dtype, o.route, o.nufft_width, o.device) == (0, 0, 12, -1)
+    assert o.defl_tol == 1e-13 and o.direct_kappa == 1e5
+
+
+@pytest.mark.parametrize("n,rho,vfill,expect", [
+    (1, 1.0, 0.0, 1),            # n < 2: EINVAL
+    (3, 1.0, 0.0, 4),            # not a power of two: EUNSUPPORTED
+    (32768, 1.0, 0.0, 4),        # above 16384: EUNSUPPORTED
+    (64, float("nan"), 0.0, 1),  # non-finite rho
+    (64, 1.0, float("inf"), 1),  # non-finite v
+])
+def test_plan_rejects_bad_arguments_on_host(lib, n, rho, vfill, expect):
+    from paper_2409_08970_amd import _binding as B
+    v = np.full(max(n, 1), vfill)
+    st, h = B.dctplus_plan(n, rho, v, check=False)
+    assert st == expect
+    assert not h.value
+    assert B.dctplus_last_error()
+
+
+def test_plan_rejects_bad_options_on_host(lib):
+    from paper_2409_08970_amd import _binding as B
+    v = np.ones(64)
+    for field, value, expect in [("dtype", 7, 1), ("route", 9, 1), ("nufft_width", 5, 1), ("nufft_width", 20, 1)]:
+        o = B.dctplus_default_opts()
+        setattr(o, field, value)
+        st, h = B.dctplus_plan(64, 1.0, v, o, check=False)
+        assert st == expect, (field, value)
+    o = B.dctplus_default_opts()
+    o.dtype = B.DCTPLUS_F64
+    o.route = B.DCTPLUS_ROUTE_DENSE
+    assert B.dctplus_plan(64, 1.0, v, o, check=False)[0] == B.DCTPLUS_EUNSUPPORTED
+    o = B.dctplus_default_opts()
+    o.dtype = B.DCTPLUS_BF16
+    o.route = B.DCTPLUS_ROUTE_FAST
+    assert B.dctplus_plan(64, 1.0, v, o, check=False)[0] == B.DCTPLUS_EUNSUPPORTED
+    # null v and null output pointer
+    assert lib.dctplus_plan(64, 1.0, None, None, None, ctypes.byref(ctypes.c_void_p())) == 1
+    assert lib.dctplus_plan(64, 1.0, None, None, None, None) == 1
+
+
+def test_calls_on_null_plan_are_rejected(lib):
+    assert lib.dctplus_forward(None, ctypes.c_void_p(16), ctypes.c_void_p(32), 4, None) == 1
+    assert lib.dctplus_adjoint(None, ctypes.c_void_p(16), ctypes.c_void_p(32), 4, None) == 1
+    assert lib.dctplus_grad(None, None, None, 4, None, None, None, None) == 1
+    assert lib.dctplus_plan_info(None, None, None, None, None, None) == 1
+    lib.dctplus_plan_destroy(None)

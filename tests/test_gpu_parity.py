@@ -1,0 +1,375 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bar (FP32 signals): max over signals of ||y - y_ref|| / ||y_ref|| <= 1e-5,
+the accuracy the paper reports for its fast transform (SNR above 100 dB,
+Sec. 5 and Table 1).  FP64 signals: 1e-12.  BF16 operands: 2e-2 (an
+8-bit-mantissa product; stated separately, never as 1e-5).
+
+Reference: the Jacobi oracle (plain definition) where the spectrum is simple
+and n <= 256; the secular semi-oracle (Thm 3.1 by bisection, itself pinned to
+Jacobi in test_oracle_pins) for larger n and for the double eigenvalues some
+added edges produce, where it fixes the canonical deflation basis.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+FAST_SKIP = pytest.mark.skip(
+    reason="FAST-route kernels are switched off: their first GPU run raised a memory-aperture fault "
+           "whose cause is not yet identified (see DESIGN.md, open issues)")
+
+TOL32 = 1e-5
+TOL64 = 1e-12
+TOLBF16 = 2e-2
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def relerr(y, yref):
+    y = np.asarray(y, dtype=np.float64)
+    yref = np.asarray(yref, dtype=np.float64)
+    num = np.linalg.norm(y - yref, axis=-1)
+    den = np.maximum(np.linalg.norm(yref, axis=-1), 1e-300)
+    return float(np.max(num / den))
+
+
+def case(n, kind, seed=0):
+    g = np.random.default_rng(10_000 + 17 * n + seed)
+    if kind == "dense":
+        return float(g.uniform(0.1, 2.0)), workloads.unit_vector(g, n)
+    if kind == "loop0":
+        v = np.zeros(n); v[0] = 1.0
+        return float(g.uniform(0.25, 2.0)), v
+    if kind == "loopn":
+        v = np.zeros(n); v[-1] = 1.0
+        return float(g.uniform(0.25, 2.0)), v
+    if kind == "edge":
+        i, j = sorted(int(t) for t in g.choice(n, 2, replace=False))
+        return 2.0, workloads.edge_vector(n, i, j)
+    if kind == "negative":
+        return -float(g.uniform(0.1, 1.0)), workloads.unit_vector(g, n)
+    raise ValueError(kind)
+
+
+_REF_CACHE = {}
+
+
+def reference(n, rho, v):
+    """(forward, adjoint) callables of the oracle for this (n, rho, v)."""
+    key = (n, rho, v.tobytes())
+    if key in _REF_CACHE:
+        return _REF_CACHE[key]
+    plan = oracle.semi_plan(n, rho, v) if rho != 0.0 else None
+    simple = True
+    if plan is not None:
+        simple = np.min(np.diff(plan["mu"])) > 1e-9
+    if n <= 256 and simple:
+        _, X = oracle.basis(n, rho, v)
+        fwd = lambda x: oracle.forward(X, x)
+        adj = lambda y: oracle.adjoint(X, y)
+    else:
+        fwd = lambda x: oracle.semi_forward(n, rho, v, x, plan)
+        adj = lambda y: oracle.semi_adjoint(n, rho, v, y, plan)
+    _REF_CACHE[key] = (fwd, adj)
+    return fwd, adj
+
+
+def run(plan, arr, adjoint=False):
+    torch = _torch()
+    dt = torch.float64 if plan.dtype == "f64" else torch.float32
+    t = torch.from_numpy(np.ascontiguousarray(arr)).to("cuda", dt)
+    out = plan.adjoint(t) if adjoint else plan.forward(t)
+    torch.cuda.synchronize()
+    return out.cpu().double().numpy()
+
+
+def make_plan(n, rho, v, route, dtype="f32", **kw):
+    _torch()
+    from paper_2409_08970_amd import Plan
+    return Plan(n, rho, v, route=route, dtype=dtype, **kw)
+
+
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [8, 64, 1024])
+@pytest.mark.parametrize("kind", ["dense", "loop0", "edge", "negative"])
+def test_plan_spectrum_matches_oracle(n, kind):
+    rho, v = case(n, kind)
+    p = make_plan(n, rho, v, "fast")
+    sp = oracle.semi_plan(n, rho, v)
+    info = p.info
+    assert np.abs(info["mu"] - sp["mu"]).max() <= 1e-12 * max(1.0, np.abs(sp["mu"]).max())
+    assert np.abs(info["z"] - sp["z"]).max() <= 1e-13
+    lam = oracle.path_eigenvalues(n)
+    a_ref = np.ones(n)
+    for i in range(n):
+        if sp["kind"][i] == 0:
+            nz = sp["z"] != 0
+            a_ref[i] = 1.0 / np.sqrt(np.sum(sp["z"][nz] ** 2 / (sp["mu"][i] - lam[nz]) ** 2))
+    assert np.abs(info["a"] - a_ref).max() <= 1e-10 * np.abs(a_ref).max()
+    assert int(info["counts"][0]) == int(np.sum(sp["kind"]))
+    p.close()
+
+
+ROUTE_SIZES = [pytest.param("fast", n, marks=FAST_SKIP) for n in (4, 8, 16, 32, 64, 128, 256, 1024)] + \
+              [("dense", n) for n in (4, 8, 16, 32, 64, 128, 256)] + \
+              [("gft", n) for n in (4, 8, 16, 32, 64, 128, 256)]
+
+
+@pytest.mark.parametrize("route,n", ROUTE_SIZES)
+@pytest.mark.parametrize("kind", ["dense", "loop0", "loopn", "edge", "negative"])
+def test_forward_and_adjoint_parity(route, n, kind):
+    rho, v = case(n, kind)
+    batch = 301                     # several tiles plus a ragged tail
+    g = np.random.default_rng(n + 7)
+    x = workloads.ar1(g, batch, n, 0.95)
+    fwd, adj = reference(n, rho, v)
+    p = make_plan(n, rho, v, route)
+    y = run(p, x)
+    assert relerr(y, fwd(x.astype(np.float64))) <= TOL32, (route, n, kind)
+    yin = g.standard_normal((batch, n)).astype(np.float32)
+    xa = run(p, yin, adjoint=True)
+    assert relerr(xa, adj(yin.astype(np.float64))) <= TOL32, (route, n, kind)
+    p.close()
+
+
+@FAST_SKIP
+@pytest.mark.parametrize("n", [4096, 16384])
+@pytest.mark.parametrize("kind", ["dense", "edge"])
+def test_large_n_full_batch_sampled(n, kind):
+    """Workload-3 shape (256 N(0,1) signals): the whole batch runs on the GPU,
+    sampled signals are checked against the semi-oracle, and the intertwining
+    property X^T (L s) = mu * X^T s and Parseval are checked on every signal."""
+    torch = _torch()
+    W = workloads.workload3(n, kind)
+    rho, v, x = W["rho"], W["v"], W["x"]
+    p = make_plan(n, rho, v, "fast")
+    y = run(p, x)
+    rows = [0, 77, 255]
+    sp = oracle.semi_plan(n, rho, v)
+    yref = oracle.semi_forward(n, rho, v, x[rows].astype(np.float64), sp)
+    assert relerr(y[rows], yref) <= TOL32
+    xr = run(p, y.astype(np.float32), adjoint=True)
+    assert relerr(xr, x) <= 2 * TOL32
+    # Parseval (X orthogonal)
+    assert np.max(np.abs(np.linalg.norm(y, axis=1) / np.linalg.norm(x, axis=1) - 1)) <= TOL32
+    # intertwining: L s for every signal (tridiagonal plus rank one, FP64 on the host)
+    xd = x.astype(np.float64)
+    Ls = 2 * xd
+    Ls[:, 0] -= xd[:, 0]
+    Ls[:, -1] -= xd[:, -1]
+    Ls[:, 1:] -= xd[:, :-1]
+    Ls[:, :-1] -= xd[:, 1:]
+    Ls += rho * np.outer(xd @ v, v)
+    yL = run(p, Ls.astype(np.float32))
+    mu = p.info["mu"]
+    assert relerr(yL, mu * y) <= 4 * TOL32
+    p.close()
+    del torch
+
+
+@pytest.mark.parametrize("route", [pytest.param("fast", marks=FAST_SKIP), "dense", "gft"])
+def test_rho_zero_and_v_zero_give_dct2(route):
+    import scipy.fft
+    n = 64
+    x = np.random.default_rng(3).standard_normal((130, n)).astype(np.float32)
+    ref = scipy.fft.dct(x.astype(np.float64), type=2, norm="ortho", axis=-1)
+    for rho, v in [(0.0, workloads.unit_vector(np.random.default_rng(1), n)), (1.5, np.zeros(n))]:
+        p = make_plan(n, rho, v, route)
+        assert relerr(run(p, x), ref) <= TOL32
+        assert int(p.info["counts"][0]) == n      # every row deflated
+        p.close()
+
+
+@pytest.mark.parametrize("route", [pytest.param("fast", marks=FAST_SKIP), "dense", "gft"])
+@pytest.mark.parametrize("n", [16, 64, 256])
+def test_double_eigenvalues_from_mirror_edge(route, n):
+    """A mirror-symmetric added edge makes a secular root land on a deflated
+    eigenvalue; the deflation basis is the canonical one (semi-oracle)."""
+    v = workloads.edge_vector(n, 2, n - 3)
+    rho = 2.0
+    x = workloads.ar1(np.random.default_rng(5), 200, n, 0.9)
+    sp = oracle.semi_plan(n, rho, v)
+    assert np.min(np.diff(sp["mu"])) < 1e-9
+    p = make_plan(n, rho, v, route)
+    assert relerr(run(p, x), oracle.semi_forward(n, rho, v, x.astype(np.float64), sp)) <= TOL32
+    p.close()
+
+
+@FAST_SKIP
+def test_fp64_self_loop_dst7():
+    """Workload 1: n = 64, unit self-loop at vertex 0, 1024 N(0,1) signals in FP64;
+    the basis is the DST-VII closed form."""
+    W = workloads.workload1()
+    n = W["n"]
+    p = make_plan(n, W["rho"], W["v"], "fast", dtype="f64")
+    y = run(p, W["x"])
+    j = np.arange(n)[:, None]
+    k = np.arange(n)[None, :]
+    X = 2.0 / np.sqrt(2 * n + 1) * np.sin(np.pi * (2 * k + 1) * (j + 1) / (2 * n + 1))
+    assert relerr(y, W["x"] @ X) <= TOL64
+    _, Xj = oracle.basis(n, W["rho"], W["v"])
+    assert relerr(y, oracle.forward(Xj, W["x"])) <= TOL64
+    xr = run(p, y, adjoint=True)
+    assert relerr(xr, W["x"]) <= TOL64
+    p.close()
+
+
+@pytest.mark.parametrize("route", ["dense", "gft"])
+@pytest.mark.parametrize("n", [32, 64])
+def test_bf16_operands(route, n):
+    rho, v = case(n, "dense")
+    x = workloads.ar1(np.random.default_rng(2), 257, n, 0.95)
+    fwd, adj = reference(n, rho, v)
+    p = make_plan(n, rho, v, route, dtype="bf16")
+    err = relerr(run(p, x), fwd(x.astype(np.float64)))
+    assert err <= TOLBF16
+    assert relerr(run(p, x, adjoint=True), adj(x.astype(np.float64))) <= TOLBF16
+    print(f"bf16 {route} n={n}: {err:.2e}")
+    p.close()
+
+
+@pytest.mark.parametrize("route", [pytest.param("fast", marks=FAST_SKIP), "dense", "gft"])
+def test_full_size_workload2_sampled(route):
+    """Workload-2 launch shape (2^20 AR(0.95) signals, n = 64): every output
+    row runs on the GPU; 2048 sampled signals are checked against Jacobi."""
+    torch = _torch()
+    W = workloads.workload2(64)
+    n, rho, v, x = W["n"], W["rho"], W["v"], W["x"]
+    p = make_plan(n, rho, v, route)
+    xt = torch.from_numpy(x).cuda()
+    y = p.forward(xt)
+    xr = p.adjoint(y)
+    torch.cuda.synchronize()
+    rows = np.random.default_rng(0).choice(x.shape[0], 2048, replace=False)
+    fwd, _ = reference(n, rho, v)
+    ys = y[torch.from_numpy(rows).cuda()].cpu().double().numpy()
+    assert relerr(ys, fwd(x[rows].astype(np.float64))) <= TOL32
+    xs = xr[torch.from_numpy(rows).cuda()].cpu().double().numpy()
+    assert relerr(xs, x[rows]) <= 2 * TOL32
+    p.close()
+
+
+def test_batch_edge_cases_and_errors():
+    torch = _torch()
+    from paper_2409_08970_amd import _binding as B
+    n = 64
+    rho, v = case(n, "dense")
+    fwd, _ = reference(n, rho, v)
+    for route in ("dense", "gft"):
+        p = make_plan(n, rho, v, route)
+        for batch in (1, 63, 64, 65, 1000):
+            x = np.random.default_rng(batch).standard_normal((batch, n)).astype(np.float32)
+            assert relerr(run(p, x), fwd(x.astype(np.float64))) <= TOL32
+        x = torch.zeros(4, n, device="cuda")
+        assert B.dctplus_forward(p.handle, x.data_ptr(), x.data_ptr(), 0, check=False) == B.DCTPLUS_OK
+        assert B.dctplus_forward(p.handle, x.data_ptr(), x.data_ptr(), 4, check=False) == B.DCTPLUS_EINVAL
+        assert B.dctplus_forward(p.handle, x.data_ptr(), x[1:].data_ptr(), 2, check=False) == B.DCTPLUS_EINVAL
+        assert B.dctplus_forward(p.handle, x.data_ptr() + 2, x[2:].data_ptr(), 1, check=False) == B.DCTPLUS_EINVAL
+        assert B.dctplus_forward(p.handle, x.data_ptr(), x[2:].data_ptr(), -1, check=False) == B.DCTPLUS_EINVAL
+        p.close()
+
+
+@pytest.mark.parametrize("route,n", [pytest.param("fast", 64, marks=FAST_SKIP),
+                                     pytest.param("fast", 4096, marks=FAST_SKIP), ("dense", 64), ("gft", 64),
+                                     ("dense", 1024), ("gft", 256)])
+def test_bitwise_determinism(route, n):
+    torch = _torch()
+    rho, v = case(n, "dense")
+    p = make_plan(n, rho, v, route)
+    x = torch.randn(513 if n <= 64 else 64, n, device="cuda")
+    a = p.forward(x)
+    b = p.forward(x)
+    c = p.adjoint(a)
+    d = p.adjoint(a)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(c, d)
+    p.close()
+
+
+# --------------------------------------------------------------------------
+# gradients
+# --------------------------------------------------------------------------
+def _gpu_grad(n, rho, v, x, route):
+    torch = _torch()
+    p = make_plan(n, rho, v, route)
+    xt = torch.from_numpy(x).cuda()
+    y = p.forward(xt)
+    gy = torch.sign(y) / y.numel()
+    gx, grho, gv = p.grad(y, gy)
+    torch.cuda.synchronize()
+    out = (y.cpu().double().numpy(), gy.cpu().double().numpy(), gx.cpu().double().numpy(), grho.item(),
+           gv.cpu().numpy())
+    p.close()
+    return out
+
+
+@pytest.mark.parametrize("route", [pytest.param("fast", marks=FAST_SKIP), "dense", "gft"])
+def test_gradient_n16_vs_oracle(route):
+    n = 16
+    W = workloads.workload5(n=n, batch=512)
+    rho, v, x = W["rho"], W["v"], W["x"]
+    y, gy, gx, grho, gv = _gpu_grad(n, rho, v, x, route)
+    mu, X = oracle.basis(n, rho, v)
+    dx, drho, dv = oracle.grad_perturbation(mu, X, rho, v, y, gy)
+    assert relerr(gx, dx) <= TOL32
+    assert abs(grho - drho) <= 1e-4 * max(abs(drho), np.abs(dv).max())
+    assert np.abs(gv - dv).max() <= 1e-4 * np.abs(dv).max()
+    # scale invariance of L in (rho, v): v . grad_v = 2 rho d/drho
+    assert abs(v @ gv - 2 * rho * grho) <= 1e-4 * np.abs(dv).max()
+
+
+def test_gradient_n256_vs_finite_differences():
+    """Workload-5 shape (n = 256, rho = 1, unit v) on 4096 signals: dl/drho and a
+    directional derivative of dl/dv against FP64 central differences (h = 1e-6)
+    of the oracle loss."""
+    n = 256
+    W = workloads.workload5(n=n, batch=4096)
+    rho, v, x = W["rho"], W["v"], W["x"]
+    y, gy, gx, grho, gv = _gpu_grad(n, rho, v, x, "dense")
+    xd = x.astype(np.float64)
+
+    def loss(r, vv):
+        return oracle.loss_l1(oracle.semi_forward(n, r, vv, xd))
+    h = 1e-6
+    fd_rho = (loss(rho + h, v) - loss(rho - h, v)) / (2 * h)
+    d = np.random.default_rng(1).standard_normal(n)
+    d /= np.linalg.norm(d)
+    fd_v = (loss(rho, v + h * d) - loss(rho, v - h * d)) / (2 * h)
+    scale = max(abs(fd_rho), np.abs(gv).max())
+    assert abs(grho - fd_rho) <= 1e-3 * scale
+    assert abs(gv @ d - fd_v) <= 1e-3 * scale
+    mu, X = oracle.basis(n, rho, v)
+    dx, drho, dv = oracle.grad_perturbation(mu, X, rho, v, y, gy)
+    assert abs(grho - drho) <= 1e-4 * scale
+    assert np.abs(gv - dv).max() <= 1e-4 * scale
+    assert relerr(gx, dx) <= TOL32
+
+
+def test_autograd_function():
+    torch = _torch()
+    from paper_2409_08970_amd import dctplus
+    n = 64
+    W = workloads.workload5(n=n, batch=1024)
+    x = torch.from_numpy(W["x"]).cuda().requires_grad_(True)
+    rho = torch.tensor(W["rho"], dtype=torch.float64, requires_grad=True)
+    v = torch.tensor(W["v"], dtype=torch.float64, requires_grad=True)
+    y = dctplus(x, rho, v)
+    loss = y.abs().mean()
+    loss.backward()
+    mu, X = oracle.basis(n, W["rho"], W["v"])
+    yd = y.detach().cpu().double().numpy()
+    dx, drho, dv = oracle.grad_perturbation(mu, X, W["rho"], W["v"], yd, np.sign(yd) / yd.size)
+    assert relerr(x.grad.cpu().double().numpy(), dx) <= TOL32
+    assert abs(rho.grad.item() - drho) <= 1e-4 * np.abs(dv).max()
+    assert np.abs(v.grad.numpy() - dv).max() <= 1e-4 * np.abs(dv).max()
