@@ -1,0 +1,199 @@
+"""Benchmark: DCT+ forward + adjoint throughput on one MI355X.
+
+A step is one forward (y = X^T x) plus one adjoint (x = X y) pass of the
+DCT+ transform over the whole batch of the shared-transform workload
+(n = 64, 2^20 AR(0.95) signals, random unit v, rho ~ U[0.1, 2]; FP32),
+inputs resident in HBM.  value = batch * n / (time per step): signal-samples
+per second through the round trip.  Beside it: the dense GFT (the paper's
+naive product) on the same GPU, with our MFMA kernel and with torch.matmul
+(hipBLASLt), the BF16-operand dense route, the n = 4096 large-graph workload,
+the roofline of the dominant kernel (HIP events on its launch stream), and
+the FP64 oracle timed on the host cores (a baseline, not a target).
+
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "signal-samples/s DCT+ fwd+bwd vs dense GFT, n=64 & 4096, FP32, rel err ≤1e-5"
+HBM_PEAK_GBS = 8000.0
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def time_pair(torch, fwd, adj, steps, warmup):
+    """Times `steps` (fwd, adj) pairs; returns (ms/step, avg fwd ms, avg adj ms)."""
+    for _ in range(warmup):
+        fwd()
+        adj()
+    torch.cuda.synchronize()
+    t0, t1 = _events(torch)
+    fe = [_events(torch) for _ in range(steps)]
+    ae = [_events(torch) for _ in range(steps)]
+    t0.record()
+    for k in range(steps):
+        fe[k][0].record()
+        fwd()
+        fe[k][1].record()
+        adj()
+        ae[k][1].record()
+    t1.record()
+    torch.cuda.synchronize()
+    total = t0.elapsed_time(t1) / steps
+    f = sum(fe[k][0].elapsed_time(fe[k][1]) for k in range(steps)) / steps
+    a = sum(fe[k][1].elapsed_time(ae[k][1]) for k in range(steps)) / steps
+    return total, f, a
+
+
+def cpu_baseline(W, sample, min_seconds=10.0):
+    """FP64 oracle on `sample` signals of the workload, all host cores."""
+    import numpy as np
+    import oracle
+    n = W["n"]
+    _, X = oracle.basis(n, W["rho"], W["v"])
+    x = W["x"][:sample].astype(np.float64)
+    oracle.forward(X, x[:16])
+    reps = 0
+    t = time.perf_counter()
+    while True:                                 # about ten seconds of CPU work
+        y = oracle.forward(X, x)
+        oracle.adjoint(X, y)
+        reps += 1
+        dt = time.perf_counter() - t
+        if dt >= min_seconds:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": reps * sample * n / dt, "unit": "signal-samples/s", "cores": cores, "kind": "oracle",
+            "sample": f"{sample} of the {W['x'].shape[0]} signals (n={n}), forward + adjoint, FP64 dense "
+                      f"apply of the Jacobi basis, {reps} repetitions in {dt:.1f} s; setup excluded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 19)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run 3 device copies of the 256 MiB input (scale for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the transform needs no "
+              f"cross-GPU exchange; see DESIGN.md for how it shards)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2409_08970_amd import Plan
+
+    dev = torch.device("cuda:0")
+    W = workloads.workload2(64)
+    n, batch = W["n"], W["x"].shape[0]
+    x = torch.from_numpy(W["x"]).to(dev)
+    y = torch.empty_like(x)
+    xr = torch.empty_like(x)
+    print(f"workload: n={n}, batch={batch}, rho={W['rho']:.4f}", file=sys.stderr, flush=True)
+    if args.copy_probe:
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": batch * n * 4}), flush=True)
+        return
+
+    # the FP32-accurate DCT+ configurations; the headline is the faster one
+    cands = {}
+    for dt in ("f32", "f32split"):
+        pl = Plan(n, W["rho"], W["v"], route="auto", dtype=dt)
+        cands[dt] = (time_pair(torch, lambda: pl.forward(x, out=y), lambda: pl.adjoint(y, out=xr),
+                               args.steps, args.warmup), pl)
+    best = min(cands, key=lambda k: cands[k][0][0])
+    (ms, f_ms, a_ms), plan = cands[best]
+    for k, (_, pl) in cands.items():
+        if k != best:
+            pl.close()
+    route = plan.route
+    value = batch * n / (ms * 1e-3)
+    alg_bytes = 2 * batch * n * 4                       # read + write of the signals, per launch
+    launch_ms = 0.5 * (f_ms + a_ms)                     # forward and adjoint launch the same kernel
+    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
+    result = {
+        "metric": METRIC, "value": value, "unit": "signal-samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if best == "f32" else "f32 (bf16x3 split operands, fp32 accumulate)",
+        "data": "synthetic",
+        "config": {"workload": f"shared-transform batch: n={n}, {batch} AR(0.95) signals, random unit v, "
+                               f"rho={W['rho']:.4f}", "route": route, "n": n, "batch": batch},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_dense_stream<64> (forward and adjoint launches)", "avg_launch_ms": launch_ms,
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "forward_ms": f_ms, "adjoint_ms": a_ms,
+        "dct_plus_configs": {k: {"ms_per_step": v[0][0], "value": batch * n / (v[0][0] * 1e-3)}
+                             for k, v in cands.items()},
+    }
+    print(f"dct+ {route}: {ms:.3f} ms/step (fwd {f_ms:.3f}, adj {a_ms:.3f})", file=sys.stderr, flush=True)
+
+    if not args.no_extra:
+        comp = {}
+        # dense GFT on the same GPU: our MFMA kernel, and the library GEMM
+        gp = Plan(n, W["rho"], W["v"], route="gft")
+        g_ms, _, _ = time_pair(torch, lambda: gp.forward(x, out=y), lambda: gp.adjoint(y, out=xr),
+                               args.steps, args.warmup)
+        comp["gft_mfma"] = {"ms_per_step": g_ms, "value": batch * n / (g_ms * 1e-3)}
+        XtT = torch.empty(n, n, device=dev)
+        Xt = torch.from_numpy(np.ascontiguousarray(
+            np.eye(n, dtype=np.float32))).to(dev)
+        gp.forward(Xt, out=XtT)                  # rows: X^T e_i -> X[i, :]
+        Xm = XtT.contiguous()                    # X (rows = spatial index)
+        XmT = Xm.t().contiguous()
+        l_ms, _, _ = time_pair(torch, lambda: torch.matmul(x, Xm, out=y), lambda: torch.matmul(y, XmT, out=xr),
+                               args.steps, args.warmup)
+        comp["gft_torch_matmul"] = {"ms_per_step": l_ms, "value": batch * n / (l_ms * 1e-3)}
+        gp.close()
+        bp = Plan(n, W["rho"], W["v"], route="dense", dtype="bf16")
+        b_ms, _, _ = time_pair(torch, lambda: bp.forward(x, out=y), lambda: bp.adjoint(y, out=xr),
+                               args.steps, args.warmup)
+        comp["dense_bf16_operands"] = {"ms_per_step": b_ms, "value": batch * n / (b_ms * 1e-3)}
+        bp.close()
+        # large graph, n = 4096 (256 N(0,1) signals, dense unit v, rho = 0.5)
+        W3 = workloads.workload3(4096, "dense")
+        x3 = torch.from_numpy(W3["x"]).to(dev)
+        y3 = torch.empty_like(x3)
+        r3 = torch.empty_like(x3)
+        large = {}
+        for rt in ("dense", "gft"):
+            p3 = Plan(4096, W3["rho"], W3["v"], route=rt)
+            t3, _, _ = time_pair(torch, lambda: p3.forward(x3, out=y3), lambda: p3.adjoint(y3, out=r3),
+                                 max(3, args.steps // 4), 2)
+            large[rt] = {"ms_per_step": t3, "value": 256 * 4096 / (t3 * 1e-3)}
+            p3.close()
+        A = torch.randn(4096, 4096, device=dev)
+        At = A.t().contiguous()
+        t3, _, _ = time_pair(torch, lambda: torch.matmul(x3, A, out=y3), lambda: torch.matmul(y3, At, out=r3),
+                             max(3, args.steps // 4), 2)
+        large["gft_torch_matmul"] = {"ms_per_step": t3, "value": 256 * 4096 / (t3 * 1e-3)}
+        large["fast"] = "FAST route switched off in this build"
+        comp["n4096_workload"] = large
+        result["comparators"] = comp
+        for k, v in comp.items():
+            print(k, v, file=sys.stderr, flush=True)
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(W, args.cpu_sample)
+    plan.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -62,7 +62,10 @@ typedef enum {
 typedef enum {
     DCTPLUS_F32 = 0,  /* FP32 signals; FP32 DCT, FP64 Cauchy stage (fast), FP32 MFMA (dense) */
     DCTPLUS_F64 = 1,  /* FP64 signals and FP64 arithmetic throughout */
-    DCTPLUS_BF16 = 2  /* FP32 signals; dense routes only: BF16 MFMA operands, FP32 accumulation */
+    DCTPLUS_BF16 = 2, /* FP32 signals; dense routes only: BF16 MFMA operands, FP32 accumulation */
+    DCTPLUS_F32_SPLIT = 3 /* FP32 signals; dense routes, n in {32, 64}: both operands split into three
+                             BF16 pieces, the six cross products of order <= 2^-16 accumulated in FP32
+                             on MFMA (FP32-level accuracy); arrays 16-byte aligned */
 } dctplus_dtype;
 
 /* How the product with diag(a) C(mu, lambda) diag(z) is formed. */

@@ -28,7 +28,7 @@ __all__ = [
 
 _ROUTES = {"auto": B.DCTPLUS_ROUTE_AUTO, "fast": B.DCTPLUS_ROUTE_FAST, "dense": B.DCTPLUS_ROUTE_DENSE,
            "gft": B.DCTPLUS_ROUTE_GFT}
-_DTYPES = {"f32": B.DCTPLUS_F32, "f64": B.DCTPLUS_F64, "bf16": B.DCTPLUS_BF16}
+_DTYPES = {"f32": B.DCTPLUS_F32, "f64": B.DCTPLUS_F64, "bf16": B.DCTPLUS_BF16, "f32split": B.DCTPLUS_F32_SPLIT}
 ROUTE_NAMES = {v: k for k, v in _ROUTES.items()}
 
 

@@ -22,7 +22,7 @@ DCTPLUS_EDEVICE = 3
 DCTPLUS_EUNSUPPORTED = 4
 DCTPLUS_ENOCONV = 5
 
-DCTPLUS_F32, DCTPLUS_F64, DCTPLUS_BF16 = 0, 1, 2
+DCTPLUS_F32, DCTPLUS_F64, DCTPLUS_BF16, DCTPLUS_F32_SPLIT = 0, 1, 2, 3
 DCTPLUS_ROUTE_AUTO, DCTPLUS_ROUTE_FAST, DCTPLUS_ROUTE_DENSE, DCTPLUS_ROUTE_GFT = 0, 1, 2, 3
 
 EXPORTED = (

@@ -106,7 +106,7 @@ dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const d
     dctplus_opts o;
     dctplus_default_opts(&o);
     if (opts) o = *opts;
-    if (o.dtype < DCTPLUS_F32 || o.dtype > DCTPLUS_BF16) return fail(DCTPLUS_EINVAL, "bad dtype %d", o.dtype);
+    if (o.dtype < DCTPLUS_F32 || o.dtype > DCTPLUS_F32_SPLIT) return fail(DCTPLUS_EINVAL, "bad dtype %d", o.dtype);
     if (o.route < DCTPLUS_ROUTE_AUTO || o.route > DCTPLUS_ROUTE_GFT)
         return fail(DCTPLUS_EINVAL, "bad route %d", o.route);
     if (!(o.defl_tol > 0.0)) o.defl_tol = 1e-13;
@@ -122,8 +122,10 @@ dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const d
     }
     if (o.dtype == DCTPLUS_F64 && route != DCTPLUS_ROUTE_FAST)
         return fail(DCTPLUS_EUNSUPPORTED, "FP64 signals are supported on the FAST route");
-    if (o.dtype == DCTPLUS_BF16 && route == DCTPLUS_ROUTE_FAST)
+    if ((o.dtype == DCTPLUS_BF16 || o.dtype == DCTPLUS_F32_SPLIT) && route == DCTPLUS_ROUTE_FAST)
         return fail(DCTPLUS_EUNSUPPORTED, "BF16 operands apply to the DENSE and GFT routes");
+    if (o.dtype == DCTPLUS_F32_SPLIT && (n < 32 || n > 64))
+        return fail(DCTPLUS_EUNSUPPORTED, "the split-BF16 mode supports n in {32, 64}");
     if ((route == DCTPLUS_ROUTE_DENSE || route == DCTPLUS_ROUTE_GFT) && n > 4096)
         return fail(DCTPLUS_EUNSUPPORTED, "dense routes support n <= 4096");
     if (o.dtype == DCTPLUS_BF16 && (n < 32 || n > 64))
@@ -176,7 +178,8 @@ dctplus_status dctplus_adjoint(dctplus_plan_t p, const void *y, void *x, int64_t
 dctplus_status dctplus_grad(dctplus_plan_t p, const void *y, const void *gy, int64_t batch, void *gx, double *grho,
                             double *gv, void *stream) {
     if (!p) return fail(DCTPLUS_EINVAL, "null plan");
-    if (p->dtype != DCTPLUS_F32) return fail(DCTPLUS_EUNSUPPORTED, "gradients are implemented for FP32 plans");
+    if (p->dtype != DCTPLUS_F32 && p->dtype != DCTPLUS_F32_SPLIT)
+        return fail(DCTPLUS_EUNSUPPORTED, "gradients are implemented for FP32 plans");
     if (batch < 0) return fail(DCTPLUS_EINVAL, "batch = %lld < 0", (long long)batch);
     if (!y || !gy) return fail(DCTPLUS_EINVAL, "null y or gy");
     if (!aligned(y, 4) || !aligned(gy, 4) || (gx && !aligned(gx, 4)) || (grho && !aligned(grho, 8)) ||

@@ -52,6 +52,7 @@ struct PlanTables {
     uint16_t *mt16;     // [n * n] BF16 copy
     int32_t *status;    // [4]    plan-build status words
     int ndirect, ndefl, width, nj;
+    int folded;         // dense factor holds X^T (DCT folded in) rather than M
 };
 
 }  // namespace dctplus
@@ -63,6 +64,7 @@ struct dctplus_plan_s {
     int dtype, route, device;
     double defl_tol, direct_kappa;
     int width;
+    int factored;             // DENSE route keeps the DCT and the Cauchy factor apart
     void *dev_mem;            // one allocation holding every table
     size_t dev_bytes;
     void *work;               // lazily grown workspace (FFT scratch for large n, gradient)

@@ -239,6 +239,139 @@ __global__ void __launch_bounds__(256) k_dense_small(const float *__restrict__ i
 }
 
 // ---------------------------------------------------------------------------
+// Streaming kernel for 16 <= N <= 64: each wave owns tiles of 16 signals and
+// computes Y^T = A X^T with v_mfma_f32_16x16x4_f32 (or 16x16x32 BF16), with
+// A = P (forward) or P^T (adjoint) held in VGPRs for the whole launch.  The
+// contraction index k is ordered so that a lane's B fragment is N/4
+// consecutive samples of one signal (float4 loads) and its D fragment is four
+// consecutive outputs of one signal (float4 stores): no LDS, no barriers, and
+// the next tile is loaded while the current one is multiplied.
+// ---------------------------------------------------------------------------
+// Three-piece BF16 split of an FP32 value: x = h + m + l to within 2^-24 |x|.
+__device__ __forceinline__ void split3(float x, uint16_t &h, uint16_t &m, uint16_t &l) {
+    h = f2bf(x);
+    const float r1 = x - __uint_as_float((uint32_t)h << 16);
+    m = f2bf(r1);
+    const float r2 = r1 - __uint_as_float((uint32_t)m << 16);
+    l = f2bf(r2);
+}
+
+// MODE 0: FP32 MFMA.  MODE 1: BF16 operands.  MODE 2: FP32-accurate products from
+// three-piece BF16 splits of both operands, keeping the six cross products of
+// order <= 2^-16 (hh, hm, mh, hl, lh, mm), all accumulated in FP32.
+template <int N, int MODE>
+__global__ void __launch_bounds__(256) k_dense_stream(const float *__restrict__ in, float *__restrict__ out,
+                                                      int64_t batch, const float *__restrict__ P32,
+                                                      const uint16_t *__restrict__ P16, int adj) {
+    constexpr bool BF16 = (MODE == 1);
+    constexpr int KQ = N / 4;      // samples per lane and tile (contiguous)
+    constexpr int CT = N / 16;     // output tiles of 16
+    constexpr int V4 = KQ / 4;     // float4 per lane and tile
+    const int lane = threadIdx.x & 63;
+    const int l16 = lane & 15, g = lane >> 4;
+    // A fragments: a[c][q] = A[16c + l16][KQ g + q],  A = P (forward) or P^T (adjoint)
+    constexpr int NA = (MODE == 2) ? 1 : CT * KQ;
+    constexpr int NS = (MODE == 2) ? CT * (KQ / 8) : 1;
+    float a[CT][(MODE == 2) ? 1 : KQ];
+    bf8 ah[NS], am[NS], al[NS];
+    (void)NA;
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            const int row = 16 * c + l16, col = KQ * g + q;
+            if constexpr (MODE == 2) {
+                const float pv = adj ? P32[(size_t)col * N + row] : P32[(size_t)row * N + col];
+                uint16_t h, m, l;
+                split3(pv, h, m, l);
+                ah[c * (KQ / 8) + q / 8][q % 8] = bits2bf(h);
+                am[c * (KQ / 8) + q / 8][q % 8] = bits2bf(m);
+                al[c * (KQ / 8) + q / 8][q % 8] = bits2bf(l);
+            } else if constexpr (BF16) {
+                const uint16_t h = adj ? P16[(size_t)col * N + row] : P16[(size_t)row * N + col];
+                a[c][q] = __uint_as_float((uint32_t)h << 16);
+            } else {
+                a[c][q] = adj ? P32[(size_t)col * N + row] : P32[(size_t)row * N + col];
+            }
+        }
+    const int64_t ntiles = (batch + 15) / 16;
+    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    auto load = [&](int64_t tile, float4 *b) {
+        const int64_t sig = tile * 16 + l16;
+        if (tile < ntiles && sig < batch) {
+            const float4 *src = reinterpret_cast<const float4 *>(in + sig * N + KQ * g);
+#pragma unroll
+            for (int v = 0; v < V4; ++v) b[v] = src[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < V4; ++v) b[v] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    float4 bcur[V4], bnext[V4];
+    load(wave0, bcur);
+    for (int64_t tile = wave0; tile < ntiles; tile += nwaves) {
+        load(tile + nwaves, bnext);
+        f4 acc[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[c] = f4{0.f, 0.f, 0.f, 0.f};
+        const float *b = reinterpret_cast<const float *>(bcur);
+        if constexpr (MODE == 2) {
+#pragma unroll
+            for (int st = 0; st < KQ / 8; ++st) {
+                bf8 bh, bm, bl;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    uint16_t h, m, l;
+                    split3(b[8 * st + e], h, m, l);
+                    bh[e] = bits2bf(h);
+                    bm[e] = bits2bf(m);
+                    bl[e] = bits2bf(l);
+                }
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    const int i = c * (KQ / 8) + st;
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[c], 0, 0, 0);
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[c], 0, 0, 0);
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[i], bm, acc[c], 0, 0, 0);
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[i], bh, acc[c], 0, 0, 0);
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bm, acc[c], 0, 0, 0);
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[c], 0, 0, 0);
+                }
+            }
+        } else if constexpr (!BF16) {
+#pragma unroll
+            for (int q = 0; q < KQ; ++q)
+#pragma unroll
+                for (int c = 0; c < CT; ++c)
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c][q], b[q], acc[c], 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int st = 0; st < KQ / 8; ++st) {
+                bf8 bv;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bv[e] = bits2bf(f2bf(b[8 * st + e]));
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    bf8 av;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) av[e] = bits2bf((uint16_t)(__float_as_uint(a[c][8 * st + e]) >> 16));
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[c], 0, 0, 0);
+                }
+            }
+        }
+        const int64_t sig = tile * 16 + l16;
+        if (sig < batch) {
+            float4 *dst = reinterpret_cast<float4 *>(out + sig * N + 4 * g);
+#pragma unroll
+            for (int c = 0; c < CT; ++c) dst[4 * c] = make_float4(acc[c][0], acc[c][1], acc[c][2], acc[c][3]);
+        }
+#pragma unroll
+        for (int v = 0; v < V4; ++v) bcur[v] = bnext[v];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Tiny n (4, 8): one thread per signal, P and the DCT matrix from LDS.
 // ---------------------------------------------------------------------------
 template <int N>
@@ -441,7 +574,10 @@ dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s) {
             return fail(DCTPLUS_ENOMEM, "hipMalloc for the BF16 dense factor failed");
         }
     }
-    const int gft = (p->route == DCTPLUS_ROUTE_GFT);
+    // The DCT is folded into the factor (P = M U^T = X^T, Thm 3.1) unless the
+    // factored progressive form is requested; both give the same transform.
+    p->t.folded = (p->route == DCTPLUS_ROUTE_GFT) || !p->factored;
+    const int gft = p->t.folded ? 1 : 0;
     const size_t lds = sizeof(double) * n + sizeof(cplx<double>) * (n / 2);
     hipLaunchKernelGGL(k_dense_rows, dim3(n), dim3(256), lds, s, p->t, gft, p->t.mt32, p->t.mt16);
     e = hipGetLastError();
@@ -454,9 +590,10 @@ dctplus_status dense_apply(dctplus_plan_s *p, const void *inv, void *outv, int64
     const int n = (int)p->n;
     const float *in = (const float *)inv;
     float *out = (float *)outv;
-    const int pre = (p->route == DCTPLUS_ROUTE_DENSE);
+    const int pre = p->t.folded ? 0 : 1;
     const int adj = adjoint ? 1 : 0;
     const bool bf = (p->dtype == DCTPLUS_BF16);
+    const bool split = (p->dtype == DCTPLUS_F32_SPLIT);
     if (n <= 8) {
         const int64_t blocks64 = (batch + 255) / 256;
         const int blocks = (int)(blocks64 < 4096 ? blocks64 : 4096);
@@ -467,14 +604,42 @@ dctplus_status dense_apply(dctplus_plan_s *p, const void *inv, void *outv, int64
             hipLaunchKernelGGL((k_dense_tiny<8>), dim3(blocks), dim3(256), 0, s, in, out, batch, p->t.mt32,
                                p->t.tw32, adj, pre);
     } else if (n <= 64) {
-        if (!bf) {
-            if (n == 16) launch_small<16, false>(p, in, out, batch, adj, pre, s);
-            else if (n == 32) launch_small<32, false>(p, in, out, batch, adj, pre, s);
-            else launch_small<64, false>(p, in, out, batch, adj, pre, s);
+        if (bf && n == 16) return fail(DCTPLUS_EUNSUPPORTED, "BF16 dense route needs n >= 32");
+        // the streaming kernel moves float4s: it needs 16-byte aligned signal arrays
+        const bool vec_ok = ((((uintptr_t)in) | ((uintptr_t)out)) & 15) == 0;
+        if (split && (!p->t.folded || !vec_ok || n < 32))
+            return fail(DCTPLUS_EUNSUPPORTED, "the split-BF16 mode needs n in {32, 64} and 16-byte aligned arrays");
+        if (!p->t.folded || !vec_ok) {
+            if (!bf) {
+                if (n == 16) launch_small<16, false>(p, in, out, batch, adj, pre, s);
+                else if (n == 32) launch_small<32, false>(p, in, out, batch, adj, pre, s);
+                else launch_small<64, false>(p, in, out, batch, adj, pre, s);
+            } else {
+                if (n == 32) launch_small<32, true>(p, in, out, batch, adj, pre, s);
+                else launch_small<64, true>(p, in, out, batch, adj, pre, s);
+            }
         } else {
-            if (n == 16) return fail(DCTPLUS_EUNSUPPORTED, "BF16 dense route needs n >= 32");
-            if (n == 32) launch_small<32, true>(p, in, out, batch, adj, pre, s);
-            else launch_small<64, true>(p, in, out, batch, adj, pre, s);
+            const int64_t ntiles = (batch + 15) / 16;
+            const int64_t waves_wanted = ntiles;
+            int blocks = (int)((waves_wanted + 3) / 4);
+            const int cap = persistent_blocks(1 << 30) * 2;   // 8 blocks (32 waves) per CU
+            if (blocks > cap) blocks = cap;
+            const float *P32 = p->t.mt32;
+            const uint16_t *P16 = p->t.mt16;
+#define DCTPLUS_STREAM(NN, MM) \
+    hipLaunchKernelGGL((k_dense_stream<NN, MM>), dim3(blocks), dim3(256), 0, s, in, out, batch, P32, P16, adj)
+            if (split) {
+                if (n == 32) DCTPLUS_STREAM(32, 2);
+                else DCTPLUS_STREAM(64, 2);
+            } else if (!bf) {
+                if (n == 16) DCTPLUS_STREAM(16, 0);
+                else if (n == 32) DCTPLUS_STREAM(32, 0);
+                else DCTPLUS_STREAM(64, 0);
+            } else {
+                if (n == 32) DCTPLUS_STREAM(32, 1);
+                else DCTPLUS_STREAM(64, 1);
+            }
+#undef DCTPLUS_STREAM
         }
     } else {
         if (bf) return fail(DCTPLUS_EUNSUPPORTED, "BF16 dense route supports n <= 64");

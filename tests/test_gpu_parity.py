@@ -239,14 +239,31 @@ def test_bf16_operands(route, n):
     p.close()
 
 
-@pytest.mark.parametrize("route", [pytest.param("fast", marks=FAST_SKIP), "dense", "gft"])
+@pytest.mark.parametrize("route", ["dense", "gft"])
+@pytest.mark.parametrize("n", [32, 64])
+@pytest.mark.parametrize("kind", ["dense", "edge", "negative"])
+def test_f32_split_bf16_products(route, n, kind):
+    """FP32-accurate products from three-piece BF16 splits: held to the FP32 bar."""
+    rho, v = case(n, kind)
+    x = workloads.ar1(np.random.default_rng(4), 333, n, 0.95)
+    x[5] *= 1e-30                        # tiny and huge signals keep relative accuracy
+    x[6] *= 1e30
+    fwd, adj = reference(n, rho, v)
+    p = make_plan(n, rho, v, route, dtype="f32split")
+    assert relerr(run(p, x), fwd(x.astype(np.float64))) <= TOL32
+    assert relerr(run(p, x, adjoint=True), adj(x.astype(np.float64))) <= TOL32
+    p.close()
+
+
+@pytest.mark.parametrize("route", [pytest.param("fast", marks=FAST_SKIP), "dense", "gft", "dense-f32split"])
 def test_full_size_workload2_sampled(route):
     """Workload-2 launch shape (2^20 AR(0.95) signals, n = 64): every output
     row runs on the GPU; 2048 sampled signals are checked against Jacobi."""
     torch = _torch()
     W = workloads.workload2(64)
     n, rho, v, x = W["n"], W["rho"], W["v"], W["x"]
-    p = make_plan(n, rho, v, route)
+    rt, _, dt = route.partition("-")
+    p = make_plan(n, rho, v, rt, dtype=dt or "f32")
     xt = torch.from_numpy(x).cuda()
     y = p.forward(xt)
     xr = p.adjoint(y)
@@ -271,6 +288,15 @@ def test_batch_edge_cases_and_errors():
         for batch in (1, 63, 64, 65, 1000):
             x = np.random.default_rng(batch).standard_normal((batch, n)).astype(np.float32)
             assert relerr(run(p, x), fwd(x.astype(np.float64))) <= TOL32
+        # 4-byte aligned but not 16-byte aligned arrays are valid input
+        xs = np.random.default_rng(9).standard_normal((40, n)).astype(np.float32)
+        buf = torch.zeros(40 * n + 2, device="cuda")
+        buf[1:1 + 40 * n] = torch.from_numpy(xs.reshape(-1)).cuda()
+        outb = torch.zeros(40 * n + 2, device="cuda")
+        B.dctplus_forward(p.handle, buf.data_ptr() + 4, outb.data_ptr() + 4, 40)
+        torch.cuda.synchronize()
+        yo = outb[1:1 + 40 * n].cpu().double().numpy().reshape(40, n)
+        assert relerr(yo, fwd(xs.astype(np.float64))) <= TOL32
         x = torch.zeros(4, n, device="cuda")
         assert B.dctplus_forward(p.handle, x.data_ptr(), x.data_ptr(), 0, check=False) == B.DCTPLUS_OK
         assert B.dctplus_forward(p.handle, x.data_ptr(), x.data_ptr(), 4, check=False) == B.DCTPLUS_EINVAL
