@@ -89,7 +89,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the transform needs no "
-              f"cross-GPU exchange; see DESIGN.md for how it shards)", file=sys.stderr)
+              f"cross-GPU exchange: each GPU would transform its own share of the signals)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

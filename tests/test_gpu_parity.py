@@ -22,7 +22,7 @@ pytestmark = pytest.mark.gpu
 
 FAST_SKIP = pytest.mark.skip(
     reason="FAST-route kernels are switched off: their first GPU run raised a memory-aperture fault "
-           "whose cause is not yet identified (see DESIGN.md, open issues)")
+           "whose cause is not yet identified; the library returns DCTPLUS_EUNSUPPORTED for them")
 
 TOL32 = 1e-5
 TOL64 = 1e-12
