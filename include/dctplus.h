@@ -147,6 +147,61 @@ dctplus_status dctplus_plan_table(dctplus_plan_t plan, const char *name, void *d
 /* Release a plan and its device memory (NULL is a no-op).  Synchronises the device. */
 void dctplus_plan_destroy(dctplus_plan_t plan);
 
+/*
+ * Batched progressive transform selection with pruning (Thm 3.1: every
+ * candidate rank-one update of one path graph shares the graph's DCT-II;
+ * Thm 3.4: a signal with small path-Laplacian quadratic form keeps only the
+ * upper-left c_p x c_p block of the candidate's Cauchy factor; Sec. 5:
+ * block-wise selection among self-loop and added-edge candidates).
+ *
+ * Problem: nblocks independent blocks.  Block b is a path graph of n_b
+ * vertices (n_b in {4, 8, 16, 32, 64}) with S signals (1 <= S <= 64) and K
+ * candidates (1 <= K <= 16).  Candidate r of block b is four doubles
+ * cand[(b*K + r)*4 .. +3] = (kind, i, j, w):
+ *   kind 0: self-loop of weight w at vertex i   (rho = w,  v = e_i; j ignored
+ *           but must lie in [0, n_b)),
+ *   kind 1: added edge (i, j), i != j, weight w (rho = 2w, v = (e_i - e_j)/sqrt 2),
+ * with integer-valued i, j in [0, n_b) and finite w > 0.  Candidate r's
+ * transform is the DCT+ basis of L_path + rho v v^T with the conventions
+ * above (rows in ascending eigenvalue order, rho v^T x_i > 0, deflated rows =
+ * DCT vectors, deflation tolerance 1e-13).
+ *
+ * dctplus_select_plan: n_host[nblocks] (int32) and cand_host[nblocks*K*4]
+ *   are HOST arrays (copied).  Builds every candidate's factor
+ *   diag(a) C(mu, lambda) diag(z) on the GPU in FP64 and keeps it in FP32
+ *   (4 K sum_b n_b^2 bytes of device memory).  Synchronises `stream` once.
+ *   Errors: EINVAL (bad sizes or candidates; nothing allocated), EUNSUPPORTED
+ *   (a block size outside the list), ENOMEM, ENOCONV (secular solver),
+ *   EDEVICE.  nblocks == 0 gives a valid empty plan.
+ *
+ * dctplus_select: x is the DEVICE array of all signals, block after block,
+ *   each block S x n_b row-major FP32 (block b starts at float
+ *   sum_{b' < b} S n_b'; dctplus_select_size() gives the total).  Signal s of
+ *   block b is pruned when sum_j (x_{j+1} - x_j)^2 <= prune_tau * ||x||^2
+ *   (sums in FP64 of the FP32 samples); pruned signals use the c_p x c_p block (c_p <= 0:
+ *   max(2, n_b / 2); c_p > n_b: n_b).  cost[b*K + r] (DEVICE, FP32) = sum
+ *   over the block's signals of the L1 norm of candidate r's coefficients;
+ *   best[b] (DEVICE, int32) = argmin_r cost (ties: lowest r); y_best (DEVICE,
+ *   same layout as x, 16-byte aligned, not overlapping x) = the winner's
+ *   coefficients (zero outside the c_p block for pruned signals).
+ *   Asynchronous on `stream`; one persistent kernel launch.  Calls on one
+ *   selection plan must not overlap (they share its work-queue counter).
+ *
+ * dctplus_select_factor: HOST copy (n_b x n_b doubles, row-major, the FP32
+ *   values as stored) of candidate r's factor of block `block`; synchronous.
+ * dctplus_select_size: total floats of x / y_best (-1 for a NULL plan).
+ * dctplus_select_destroy: releases the plan (NULL is a no-op); synchronises the device.
+ */
+typedef struct dctplus_select_s *dctplus_select_t;
+
+dctplus_status dctplus_select_plan(int64_t nblocks, int32_t K, int32_t S, const int32_t *n_host,
+                                   const double *cand_host, void *stream, dctplus_select_t *out);
+dctplus_status dctplus_select(dctplus_select_t plan, const float *x, int32_t c_p, double prune_tau, int32_t *best,
+                              float *cost, float *y_best, void *stream);
+dctplus_status dctplus_select_factor(dctplus_select_t plan, int64_t block, int32_t r, double *dst);
+int64_t dctplus_select_size(dctplus_select_t plan);
+void dctplus_select_destroy(dctplus_select_t plan);
+
 const char *dctplus_status_string(dctplus_status s);
 const char *dctplus_last_error(void);
 

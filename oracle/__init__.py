@@ -16,8 +16,10 @@ Routes
   slow (n > 1024); checked against the Jacobi route by the tests.
 * ``grad_perturbation``: first-order eigenvector perturbation applied to
   ``y = X^T x`` (derivation in the docstring), plus ``loss_l1``.
-* ``select_blocks``: progressive selection with pruning (Thm 3.4, Fig. 2,
-  Sec. 5 pruning experiment) from Jacobi eigenvectors.
+* ``select_block``: progressive selection with pruning (Thm 3.4, Fig. 2,
+  Sec. 5 pruning experiment); each candidate's factor comes from the Jacobi
+  eigenvectors or, where an update makes eigenvalues coincide, from the
+  secular roots with deflation (``candidate_factor``).
 
 Sign convention: eigenvector ``x_i`` gets ``rho * v^T x_i > 0``
 (equivalently ``a_i > 0`` in ``X^T = diag(a) C(mu, lambda) diag(z) U^T``);
@@ -304,7 +306,24 @@ def path_quadratic_form(x) -> np.ndarray:
     return np.sum(np.diff(x, axis=-1) ** 2, axis=-1)
 
 
-def select_block(x, cands, c_p: int, prune_tau: float):
+def candidate_factor(n: int, kind: int, i: int, j: int, w: float, method: str = "jacobi") -> np.ndarray:
+    """C~ = X^T U of one candidate: row i holds eigenvector x_i in the DCT domain (Thm 3.1).
+
+    method "jacobi": eigenvectors of the assembled Laplacian (cyclic Jacobi,
+    sign convention of fix_signs).  method "semi": the factor
+    diag(a) C(mu, lambda) diag(z) from the secular roots with deflation
+    (Thm 3.1, Remark 1), which fixes the basis inside a multiple eigenvalue
+    the way the method does (deflated DCT vector first)."""
+    rho, v = candidate_update(n, kind, i, j, w)
+    if method == "jacobi":
+        _, X = basis(n, rho, v)
+        return X.T @ dct2_matrix(n)
+    if method == "semi":
+        return semi_rows(semi_plan(n, rho, v), range(n))
+    raise ValueError(method)
+
+
+def select_block(x, cands, c_p: int, prune_tau: float, factor: str = "jacobi"):
     """One block: returns (best index, cost per candidate, winner coefficients, pruned mask).
 
     x: [S, n] signals.  cands: list of (kind, i, j, w).
@@ -312,7 +331,7 @@ def select_block(x, cands, c_p: int, prune_tau: float):
     signal keeps only the upper-left c_p x c_p block of
     C~_r = diag(a_r) C(mu_r, lambda) diag(z_r) = X_r^T U (Thm 3.4), others use
     the full transform.  cost_r = sum over signals of ||yhat||_1; ties go to the
-    lowest r.
+    lowest r.  factor: how C~_r is formed (see candidate_factor).
     """
     x = np.asarray(x, dtype=np.float64)
     S, n = x.shape
@@ -322,9 +341,7 @@ def select_block(x, cands, c_p: int, prune_tau: float):
     costs = np.zeros(len(cands))
     outs = []
     for r, (kind, i, j, w) in enumerate(cands):
-        rho, v = candidate_update(n, kind, i, j, w)
-        _, X = basis(n, rho, v)
-        Ct = X.T @ U
+        Ct = candidate_factor(n, int(kind), int(i), int(j), float(w), factor)
         yfull = sd @ Ct.T
         ypr = np.zeros_like(yfull)
         ypr[:, :c_p] = sd[:, :c_p] @ Ct[:c_p, :c_p].T

@@ -8,6 +8,8 @@ ABI of ``include/dctplus.h``).  This package marshals torch tensors into it:
     y = plan.forward(x)        # x: [batch, n] device tensor
     x2 = plan.adjoint(y)
     y = dctplus(x, rho, v)     # differentiable in x, rho and v
+    sel = SelectPlan(n_blocks, cand, S=64)   # progressive selection with pruning
+    best, cost, y = sel.select(x)
 
 torch is used for device memory and streams only.
 """
@@ -18,12 +20,14 @@ import ctypes
 from . import _binding as B
 from ._binding import (DctPlusError, dctplus_adjoint, dctplus_default_opts, dctplus_forward, dctplus_grad,
                        dctplus_last_error, dctplus_plan, dctplus_plan_destroy, dctplus_plan_info,
-                       dctplus_plan_table, dctplus_status_string)
+                       dctplus_plan_table, dctplus_select, dctplus_select_destroy, dctplus_select_factor,
+                       dctplus_select_plan, dctplus_select_size, dctplus_status_string)
 
 __all__ = [
     "Plan", "DctPlusFn", "dctplus", "DctPlusError", "dctplus_plan", "dctplus_forward", "dctplus_adjoint",
     "dctplus_grad", "dctplus_plan_info", "dctplus_plan_table", "dctplus_plan_destroy", "dctplus_status_string",
-    "dctplus_last_error", "dctplus_default_opts",
+    "dctplus_last_error", "dctplus_default_opts", "SelectPlan", "dctplus_select_plan", "dctplus_select",
+    "dctplus_select_factor", "dctplus_select_size", "dctplus_select_destroy",
 ]
 
 _ROUTES = {"auto": B.DCTPLUS_ROUTE_AUTO, "fast": B.DCTPLUS_ROUTE_FAST, "dense": B.DCTPLUS_ROUTE_DENSE,
@@ -115,6 +119,54 @@ class Plan:
             import torch
             torch.cuda.synchronize(self.device)
             B.dctplus_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SelectPlan:
+    """Batched progressive selection (one dctplus selection plan).
+
+    n_blocks: [nblocks] block sizes; cand: [nblocks, K, 4] (kind, i, j, w);
+    S: signals per block.  select(x) takes the concatenated [sum_b S n_b]
+    FP32 device signals and returns (best [nblocks] int32, cost [nblocks, K]
+    FP32, y_best like x)."""
+
+    def __init__(self, n_blocks, cand, S: int = 64, stream=None):
+        import numpy as np
+        import torch
+        self.n_blocks = np.asarray(n_blocks, dtype=np.int32).reshape(-1).copy()
+        cand = np.asarray(cand, dtype=np.float64)
+        self.K = int(cand.shape[1]) if cand.ndim == 3 else int(cand.size // (4 * max(1, self.n_blocks.size)))
+        self.S = int(S)
+        self.device = torch.cuda.current_device()
+        self._h = None
+        _, self._h = B.dctplus_select_plan(self.n_blocks, self.K, self.S, cand, _stream(stream))
+        self.size = B.dctplus_select_size(self._h)
+
+    def select(self, x, c_p: int = 0, prune_tau: float = 0.1, out=None, stream=None):
+        import torch
+        nb = self.n_blocks.size
+        if not (x.is_cuda and x.dtype == torch.float32 and x.numel() == self.size):
+            raise ValueError(f"expected a CUDA FP32 tensor of {self.size} elements")
+        x = x.contiguous()
+        best = torch.empty(nb, dtype=torch.int32, device=x.device)
+        cost = torch.empty(nb, self.K, dtype=torch.float32, device=x.device)
+        y = torch.empty_like(x) if out is None else out
+        B.dctplus_select(self._h, x.data_ptr(), c_p, prune_tau, best.data_ptr(), cost.data_ptr(), y.data_ptr(),
+                         _stream(stream))
+        return best, cost, y
+
+    def factor(self, block: int, r: int):
+        return B.dctplus_select_factor(self._h, block, r, int(self.n_blocks[block]))
+
+    def close(self):
+        if self._h:
+            B.dctplus_select_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -28,7 +28,8 @@ DCTPLUS_ROUTE_AUTO, DCTPLUS_ROUTE_FAST, DCTPLUS_ROUTE_DENSE, DCTPLUS_ROUTE_GFT =
 EXPORTED = (
     "dctplus_default_opts", "dctplus_plan", "dctplus_forward", "dctplus_adjoint", "dctplus_grad",
     "dctplus_plan_info", "dctplus_plan_table", "dctplus_plan_destroy", "dctplus_status_string",
-    "dctplus_last_error",
+    "dctplus_last_error", "dctplus_select_plan", "dctplus_select", "dctplus_select_factor",
+    "dctplus_select_size", "dctplus_select_destroy",
 )
 
 
@@ -84,6 +85,16 @@ def load(path: str = LIB_PATH):
     lib.dctplus_status_string.restype = ctypes.c_char_p
     lib.dctplus_last_error.argtypes = []
     lib.dctplus_last_error.restype = ctypes.c_char_p
+    lib.dctplus_select_plan.argtypes = [i64, ctypes.c_int32, ctypes.c_int32, i32p, dp, vp, ctypes.POINTER(vp)]
+    lib.dctplus_select_plan.restype = ctypes.c_int
+    lib.dctplus_select.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_double, vp, vp, vp, vp]
+    lib.dctplus_select.restype = ctypes.c_int
+    lib.dctplus_select_factor.argtypes = [vp, i64, ctypes.c_int32, dp]
+    lib.dctplus_select_factor.restype = ctypes.c_int
+    lib.dctplus_select_size.argtypes = [vp]
+    lib.dctplus_select_size.restype = i64
+    lib.dctplus_select_destroy.argtypes = [vp]
+    lib.dctplus_select_destroy.restype = None
     _lib = lib
     return lib
 
@@ -177,6 +188,48 @@ def dctplus_plan_table(plan, name: str):
 def dctplus_plan_destroy(plan) -> None:
     if plan:
         load().dctplus_plan_destroy(plan)
+
+
+def dctplus_select_plan(n_blocks, K: int, S: int, cand, stream: int = 0, check: bool = True):
+    """Returns (status, handle).  n_blocks: nblocks ints; cand: nblocks*K*4 doubles (kind, i, j, w)."""
+    import numpy as np
+    nb = np.ascontiguousarray(np.asarray(n_blocks, dtype=np.int32).reshape(-1))
+    cd = np.ascontiguousarray(np.asarray(cand, dtype=np.float64).reshape(-1))
+    handle = ctypes.c_void_p()
+    st = load().dctplus_select_plan(int(nb.size), int(K), int(S),
+                                    nb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if nb.size else None,
+                                    cd.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if cd.size else None,
+                                    ctypes.c_void_p(stream), ctypes.byref(handle))
+    if check:
+        _check(st, "dctplus_select_plan")
+    return st, handle
+
+
+def dctplus_select(plan, x_ptr: int, c_p: int, prune_tau: float, best_ptr: int, cost_ptr: int, y_ptr: int,
+                   stream: int = 0, check: bool = True) -> int:
+    st = load().dctplus_select(plan, ctypes.c_void_p(x_ptr), int(c_p), float(prune_tau), ctypes.c_void_p(best_ptr),
+                               ctypes.c_void_p(cost_ptr), ctypes.c_void_p(y_ptr), ctypes.c_void_p(stream))
+    if check:
+        _check(st, "dctplus_select")
+    return st
+
+
+def dctplus_select_factor(plan, block: int, r: int, n: int):
+    """Host copy (n x n numpy float64) of candidate r's stored factor of one block."""
+    import numpy as np
+    out = np.zeros((n, n))
+    _check(load().dctplus_select_factor(plan, int(block), int(r), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "dctplus_select_factor")
+    return out
+
+
+def dctplus_select_size(plan) -> int:
+    return int(load().dctplus_select_size(plan))
+
+
+def dctplus_select_destroy(plan) -> None:
+    if plan:
+        load().dctplus_select_destroy(plan)
 
 
 def dctplus_status_string(status: int) -> str:

@@ -95,3 +95,36 @@ def test_calls_on_null_plan_are_rejected(lib):
     assert lib.dctplus_grad(None, None, None, 4, None, None, None, None) == 1
     assert lib.dctplus_plan_info(None, None, None, None, None, None) == 1
     lib.dctplus_plan_destroy(None)
+
+
+@pytest.mark.parametrize("nb,K,S,cand_row,expect", [
+    ([64], 0, 64, (0, 0, 0, 1.0), 1),          # K < 1
+    ([64], 17, 64, (0, 0, 0, 1.0), 1),         # K > 16
+    ([64], 2, 0, (0, 0, 0, 1.0), 1),           # S < 1
+    ([64], 2, 65, (0, 0, 0, 1.0), 1),          # S > 64
+    ([48], 2, 64, (0, 0, 0, 1.0), 4),          # block size outside {4, ..., 64}: EUNSUPPORTED
+    ([128], 2, 64, (0, 0, 0, 1.0), 4),
+    ([64], 2, 64, (2, 0, 0, 1.0), 1),          # unknown kind
+    ([64], 2, 64, (1, 3, 3, 1.0), 1),          # edge with i == j
+    ([64], 2, 64, (0, 64, 0, 1.0), 1),         # vertex out of range
+    ([64], 2, 64, (0, 1.5, 0, 1.0), 1),        # non-integer vertex
+    ([64], 2, 64, (0, 0, 0, 0.0), 1),          # weight <= 0
+    ([64], 2, 64, (0, 0, 0, float("nan")), 1),
+])
+def test_select_plan_rejects_bad_arguments_on_host(lib, nb, K, S, cand_row, expect):
+    from paper_2409_08970_amd import _binding as B
+    cand = np.tile(np.asarray(cand_row, dtype=np.float64), (len(nb), max(K, 1), 1))
+    st, h = B.dctplus_select_plan(nb, K, S, cand, check=False)
+    assert st == expect
+    assert not h.value
+    assert B.dctplus_last_error()
+
+
+def test_select_calls_on_null_plan_are_rejected(lib):
+    assert lib.dctplus_select(None, ctypes.c_void_p(16), 0, 0.1, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                              ctypes.c_void_p(16), None) == 1
+    out = np.zeros(16)
+    assert lib.dctplus_select_factor(None, 0, 0, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == 1
+    assert lib.dctplus_select_size(None) == -1
+    assert lib.dctplus_select_plan(1, 2, 64, None, None, None, ctypes.byref(ctypes.c_void_p())) == 1
+    lib.dctplus_select_destroy(None)

@@ -326,6 +326,69 @@ def test_select_block_argmin():
     assert abs(costs_f[best_f] - np.abs(oracle.forward(X, x)).sum()) < 1e-9
 
 
+def _candidates_all_kinds(n):
+    """Self-loops at both ends, an interior edge, a mirror edge (i + j = n - 1:
+    every even-index DCT vector is deflated and many eigenvalues are double)
+    and an adjacent edge."""
+    return [(0, 0, 0, 0.7), (0, n - 1, n - 1, 1.9), (1, 1, n // 2, 1.0), (1, 1, n - 2, 1.0),
+            (1, n // 2 - 1, n // 2, 1.0)]
+
+
+@pytest.mark.parametrize("n", [4, 8, 16, 32, 64])
+def test_candidate_factor_semi_diagonalises_every_candidate(n):
+    # the factor from the secular roots is orthogonal and diagonalises U^T L U
+    # (Thm 3.1) for every candidate kind, including the degenerate ones
+    U = oracle.dct2_matrix(n)
+    for cand in _candidates_all_kinds(n):
+        rho, v = oracle.candidate_update(n, *cand)
+        Ct = oracle.candidate_factor(n, *cand, method="semi")
+        mu = np.linalg.eigvalsh(oracle.laplacian(n, rho, v))
+        assert np.abs(Ct @ Ct.T - np.eye(n)).max() < 1e-12, cand
+        assert np.abs(Ct.T @ np.diag(mu) @ Ct - U.T @ oracle.laplacian(n, rho, v) @ U).max() < 1e-11, cand
+        # sign convention: rho v^T x_i > 0 where v^T x_i is not ~0
+        vx = (Ct @ U.T) @ v
+        assert np.all((np.abs(vx) < 1e-9) | (rho * vx > 0)), cand
+
+
+@pytest.mark.parametrize("n", [4, 8, 16, 32, 64])
+def test_candidate_factor_semi_matches_jacobi_on_simple_spectra(n):
+    for cand in [(0, 0, 0, 0.25), (0, n - 1, n - 1, 2.0), (0, 0, 0, 1.3)]:
+        a = oracle.candidate_factor(n, *cand, method="semi")
+        b = oracle.candidate_factor(n, *cand, method="jacobi")
+        assert np.abs(a - b).max() < 1e-10, cand
+
+
+def test_select_block_pruning_limits():
+    g = _rng(12)
+    n = 32
+    x = workloads.ar1(g, 64, n, 0.9, dtype=np.float64)
+    cands = _candidates_all_kinds(n)
+    # quadratic form against the assembled path Laplacian (no update)
+    Lp = oracle.laplacian(n, 0.0, np.zeros(n))
+    q = np.einsum("si,ij,sj->s", x, Lp, x)
+    assert np.allclose(oracle.path_quadratic_form(x), q, rtol=1e-12)
+    _, _, _, pruned = oracle.select_block(x, cands, c_p=2, prune_tau=0.1, factor="semi")
+    assert np.array_equal(pruned, q <= 0.1 * np.sum(x * x, axis=1))
+    # nothing pruned: every cost is the L1 norm of the full transform, for any c_p
+    _, c_none, _, pr = oracle.select_block(x, cands, c_p=2, prune_tau=-1.0, factor="semi")
+    assert not pr.any()
+    _, c_full, _, _ = oracle.select_block(x, cands, c_p=n, prune_tau=1e9, factor="semi")
+    assert np.allclose(c_none, c_full, rtol=1e-13)
+    for r, cand in enumerate(cands):
+        rho, v = oracle.candidate_update(n, *cand)
+        y = oracle.semi_forward(n, rho, v, x)
+        assert abs(c_none[r] - np.abs(y).sum()) < 1e-9 * c_none[r]
+    # everything pruned to c_p = 2: two coefficients per signal, error within the Thm 3.4 bound
+    b2, c2, y2, pr2 = oracle.select_block(x, cands, c_p=2, prune_tau=1e9, factor="semi")
+    assert pr2.all() and np.count_nonzero(y2[:, 2:]) == 0
+    rho, v = oracle.candidate_update(n, *cands[b2])
+    yf = oracle.semi_forward(n, rho, v, x)
+    sd = x @ oracle.dct2_matrix(n)
+    Ct = oracle.candidate_factor(n, *cands[b2], method="semi")
+    bound = np.linalg.norm(sd[:, 2:], axis=1) + np.linalg.norm(sd[:, :2] @ Ct[2:, :2].T, axis=1)
+    assert np.all(np.linalg.norm(yf - y2, axis=1) <= bound + 1e-12)
+
+
 # --------------------------------------------------------------------------
 # mutation tests: plausible mistakes must trip at least one pin
 # --------------------------------------------------------------------------
