@@ -61,7 +61,8 @@ typedef enum {
 /* Element type of signals, and the arithmetic of the bulk of the transform. */
 typedef enum {
     DCTPLUS_F32 = 0,  /* FP32 signals; FP32 DCT, FP64 Cauchy stage (fast), FP32 MFMA (dense) */
-    DCTPLUS_F64 = 1,  /* FP64 signals and FP64 arithmetic throughout */
+    DCTPLUS_F64 = 1,  /* FP64 signals and FP64 arithmetic throughout (dense routes: FP64 MFMA
+                         product with the FP64 X^T, 8 n^2 bytes) */
     DCTPLUS_BF16 = 2, /* FP32 signals; dense routes only: BF16 MFMA operands, FP32 accumulation */
     DCTPLUS_F32_SPLIT = 3 /* FP32 signals; dense routes, n in {32, 64}: both operands split into three
                              BF16 pieces, the six cross products of order <= 2^-16 accumulated in FP32
@@ -70,7 +71,7 @@ typedef enum {
 
 /* How the product with diag(a) C(mu, lambda) diag(z) is formed. */
 typedef enum {
-    DCTPLUS_ROUTE_AUTO = 0,  /* DENSE for n <= 64, FAST above (F32); FAST for F64 */
+    DCTPLUS_ROUTE_AUTO = 0,  /* DENSE for n <= 4096, FAST above */
     DCTPLUS_ROUTE_FAST = 1,  /* Alg. 1 / Thm 3.3: DCT-II, DST-I, sine NUFFT, O(n log n) */
     DCTPLUS_ROUTE_DENSE = 2, /* Thm 3.1: DCT-II, then an MFMA product with the n x n Cauchy factor */
     DCTPLUS_ROUTE_GFT = 3    /* dense GFT (the paper's naive product): MFMA product with X^T */

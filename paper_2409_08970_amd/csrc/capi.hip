@@ -116,12 +116,9 @@ dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const d
         return fail(DCTPLUS_EINVAL, "nufft_width %d: must be even, 4..%d", o.nufft_width, kMaxWidth);
     int route = o.route;
     if (route == DCTPLUS_ROUTE_AUTO) {
-        if (o.dtype == DCTPLUS_F64) route = DCTPLUS_ROUTE_FAST;
-        else if (o.dtype == DCTPLUS_BF16) route = DCTPLUS_ROUTE_DENSE;
-        else route = DCTPLUS_ROUTE_DENSE;   // the FAST kernels are switched off in this build
+        // the FAST kernels are switched off in this build: every dtype takes the dense form
+        route = (n <= 4096) ? DCTPLUS_ROUTE_DENSE : DCTPLUS_ROUTE_FAST;
     }
-    if (o.dtype == DCTPLUS_F64 && route != DCTPLUS_ROUTE_FAST)
-        return fail(DCTPLUS_EUNSUPPORTED, "FP64 signals are supported on the FAST route");
     if ((o.dtype == DCTPLUS_BF16 || o.dtype == DCTPLUS_F32_SPLIT) && route == DCTPLUS_ROUTE_FAST)
         return fail(DCTPLUS_EUNSUPPORTED, "BF16 operands apply to the DENSE and GFT routes");
     if (o.dtype == DCTPLUS_F32_SPLIT && (n < 32 || n > 64))
@@ -252,6 +249,7 @@ void dctplus_plan_destroy(dctplus_plan_t p) {
     if (p->t.direct) (void)hipFree(p->t.direct);
     if (p->t.mt32) (void)hipFree(p->t.mt32);
     if (p->t.mt16) (void)hipFree(p->t.mt16);
+    if (p->t.mt64) (void)hipFree(p->t.mt64);
     if (p->work) (void)hipFree(p->work);
     if (p->dev_mem) (void)hipFree(p->dev_mem);
     if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);

@@ -50,6 +50,7 @@ struct PlanTables {
     // DENSE / GFT routes
     float *mt32;        // [n * n] column-major M (M^T row-major) or X^T for GFT
     uint16_t *mt16;     // [n * n] BF16 copy
+    double *mt64;       // [n * n] FP64 X^T (FP64 plans)
     int32_t *status;    // [4]    plan-build status words
     int ndirect, ndefl, width, nj;
     int folded;         // dense factor holds X^T (DCT folded in) rather than M

@@ -38,7 +38,7 @@ __device__ __forceinline__ __bf16 bits2bf(uint16_t b) {
 // P rows in FP64 -> optional DCT-III along the row (GFT) -> FP32 / BF16.
 // One workgroup per row; LDS: n doubles + n/2 complex doubles.
 __global__ void __launch_bounds__(256) k_dense_rows(PlanTables t, int gft, float *__restrict__ P32,
-                                                    uint16_t *__restrict__ P16) {
+                                                    uint16_t *__restrict__ P16, double *__restrict__ P64) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = t.n, logn = t.logn, i = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
     double *row = reinterpret_cast<double *>(smem);
@@ -71,13 +71,15 @@ __global__ void __launch_bounds__(256) k_dense_rows(PlanTables t, int gft, float
         fft_dif(Z, 1, n / 2, logn - 1, t.tw64, logT, rp);
         for (int j = tid; j < n; j += nthr) {
             const double v = dct3_sample(Z, j, logn, rp);
-            P32[(size_t)i * n + j] = (float)v;
+            if (P32) P32[(size_t)i * n + j] = (float)v;
             if (P16) P16[(size_t)i * n + j] = f2bf((float)v);
+            if (P64) P64[(size_t)i * n + j] = v;
         }
     } else {
         for (int j = tid; j < n; j += nthr) {
-            P32[(size_t)i * n + j] = (float)row[j];
+            if (P32) P32[(size_t)i * n + j] = (float)row[j];
             if (P16) P16[(size_t)i * n + j] = f2bf((float)row[j]);
+            if (P64) P64[(size_t)i * n + j] = row[j];
         }
     }
 }
@@ -532,6 +534,68 @@ __global__ void __launch_bounds__(256) k_gemm(const float *__restrict__ A, const
             }
 }
 
+// FP64 product for FP64 plans, any n >= 4: C[b][j] = sum_k A[b][k] B[k][j] with
+// B[k][j] = P[j][k] (transB, forward y = P x) or P[k][j] (adjoint x = P^T y).
+// 64 x 64 output tiles, 2 x 2 waves of 32 x 32 on 16x16x4 FP64 MFMA, k-steps of
+// 16 through LDS; every load and store is bounds-checked, so n need not be a
+// multiple of the tile.
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_gemm64(const double *__restrict__ A, const double *__restrict__ P,
+                                                double *__restrict__ C, int64_t batch, int n, int transB) {
+    __shared__ double As[TBM][TBK + 1];
+    __shared__ double Bs[TBK][TBN + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int64_t m0 = (int64_t)blockIdx.y * TBM;
+    const int n0 = blockIdx.x * TBN;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    d4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < n; k0 += TBK) {
+        for (int e = tid; e < TBM * TBK; e += 256) {
+            const int r = e / TBK, k = e % TBK;
+            const int64_t row = m0 + r;
+            As[r][k] = (row < batch && k0 + k < n) ? A[row * n + k0 + k] : 0.0;
+        }
+        for (int e = tid; e < TBK * TBN; e += 256) {
+            int k, j;
+            if (transB) { j = e / TBK; k = e % TBK; }
+            else { k = e / TBN; j = e % TBN; }
+            const bool in = (k0 + k < n) && (n0 + j < n);
+            Bs[k][j] = !in ? 0.0 : transB ? P[(size_t)(n0 + j) * n + k0 + k] : P[(size_t)(k0 + k) * n + n0 + j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < TBK / 4; ++s) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const double av = As[wm + 16 * a + l16][4 * s + lq];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const double bv = Bs[4 * s + lq][wn + 16 * b + l16];
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[a][b], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                // the FP64 16x16x4 product leaves element v of lane l at row 4 v + l / 16
+                const int64_t row = m0 + wm + 16 * a + 4 * v + lq;
+                const int col = n0 + wn + 16 * b + l16;
+                if (row < batch && col < n) C[row * n + col] = acc[a][b][v];
+            }
+}
+
 int persistent_blocks(int64_t nchunks) {
     static int ncu = 0;
     if (ncu == 0) {
@@ -560,7 +624,24 @@ void launch_small(const dctplus_plan_s *p, const float *in, float *out, int64_t 
 dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s) {
     const int n = (int)p->n;
     const size_t elems = (size_t)n * n;
-    hipError_t e = hipMalloc(&p->t.mt32, sizeof(float) * elems);
+    hipError_t e;
+    if (p->dtype == DCTPLUS_F64) {
+        // FP64 plans keep only the FP64 X^T (the DCT is always folded in)
+        e = hipMalloc(&p->t.mt64, sizeof(double) * elems);
+        if (e != hipSuccess) {
+            p->t.mt64 = nullptr;
+            (void)hipGetLastError();
+            return fail(DCTPLUS_ENOMEM, "hipMalloc for the %d x %d FP64 dense factor failed", n, n);
+        }
+        p->t.folded = 1;
+        const size_t lds = sizeof(double) * n + sizeof(cplx<double>) * (n / 2);
+        hipLaunchKernelGGL(k_dense_rows, dim3(n), dim3(256), lds, s, p->t, 1, (float *)nullptr,
+                           (uint16_t *)nullptr, p->t.mt64);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "dense factor build");
+        return DCTPLUS_OK;
+    }
+    e = hipMalloc(&p->t.mt32, sizeof(float) * elems);
     if (e != hipSuccess) {
         p->t.mt32 = nullptr;
         (void)hipGetLastError();
@@ -579,7 +660,8 @@ dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s) {
     p->t.folded = (p->route == DCTPLUS_ROUTE_GFT) || !p->factored;
     const int gft = p->t.folded ? 1 : 0;
     const size_t lds = sizeof(double) * n + sizeof(cplx<double>) * (n / 2);
-    hipLaunchKernelGGL(k_dense_rows, dim3(n), dim3(256), lds, s, p->t, gft, p->t.mt32, p->t.mt16);
+    hipLaunchKernelGGL(k_dense_rows, dim3(n), dim3(256), lds, s, p->t, gft, p->t.mt32, p->t.mt16,
+                       (double *)nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "dense factor build");
     return DCTPLUS_OK;
@@ -594,6 +676,16 @@ dctplus_status dense_apply(dctplus_plan_s *p, const void *inv, void *outv, int64
     const int adj = adjoint ? 1 : 0;
     const bool bf = (p->dtype == DCTPLUS_BF16);
     const bool split = (p->dtype == DCTPLUS_F32_SPLIT);
+    if (p->dtype == DCTPLUS_F64) {
+        // y = X^T x (or x = X y) as one FP64 product with the folded factor
+        if (batch > (int64_t)65535 * TBM) return fail(DCTPLUS_EINVAL, "batch too large for the FP64 dense route");
+        const dim3 grid((unsigned)((n + TBN - 1) / TBN), (unsigned)((batch + TBM - 1) / TBM));
+        hipLaunchKernelGGL(k_gemm64, grid, dim3(256), 0, s, (const double *)inv, (const double *)p->t.mt64,
+                           (double *)outv, batch, n, adjoint ? 0 : 1);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "FP64 dense route launch");
+        return DCTPLUS_OK;
+    }
     if (n <= 8) {
         const int64_t blocks64 = (batch + 255) / 256;
         const int blocks = (int)(blocks64 < 4096 ? blocks64 : 4096);

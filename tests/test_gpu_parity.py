@@ -206,13 +206,13 @@ def test_double_eigenvalues_from_mirror_edge(route, n):
     p.close()
 
 
-@FAST_SKIP
-def test_fp64_self_loop_dst7():
+@pytest.mark.parametrize("route", [pytest.param("fast", marks=FAST_SKIP), "dense", "gft", "auto"])
+def test_fp64_self_loop_dst7(route):
     """Workload 1: n = 64, unit self-loop at vertex 0, 1024 N(0,1) signals in FP64;
     the basis is the DST-VII closed form."""
     W = workloads.workload1()
     n = W["n"]
-    p = make_plan(n, W["rho"], W["v"], "fast", dtype="f64")
+    p = make_plan(n, W["rho"], W["v"], route, dtype="f64")
     y = run(p, W["x"])
     j = np.arange(n)[:, None]
     k = np.arange(n)[None, :]
@@ -223,6 +223,35 @@ def test_fp64_self_loop_dst7():
     xr = run(p, y, adjoint=True)
     assert relerr(xr, W["x"]) <= TOL64
     p.close()
+
+
+@pytest.mark.parametrize("route", ["dense", "gft"])
+@pytest.mark.parametrize("n", [4, 8, 16, 32, 64, 128, 256, 1024])
+@pytest.mark.parametrize("kind", ["dense", "loopn", "edge", "negative"])
+def test_fp64_dense_parity(route, n, kind):
+    """FP64 signals: 1e-12 against the secular semi-oracle, and against the
+    Jacobi eigenvectors (simple spectra, n <= 256) within their own conditioning,
+    100 eps ||L|| / (smallest eigenvalue gap): the first-order error bound of a
+    backward-stable eigensolver, which exceeds 1e-12 once gaps fall below ~1e-3."""
+    rho, v = case(n, kind)
+    batch = 75                      # one full 64-signal tile and a ragged tail
+    g = np.random.default_rng(3 * n + 1)
+    x = g.standard_normal((batch, n))
+    yin = g.standard_normal((batch, n))
+    p = make_plan(n, rho, v, route, dtype="f64")
+    y = run(p, x)
+    xa = run(p, yin, adjoint=True)
+    p.close()
+    sp = oracle.semi_plan(n, rho, v)
+    assert relerr(y, oracle.semi_forward(n, rho, v, x, sp)) <= TOL64, (route, n, kind)
+    assert relerr(xa, oracle.semi_adjoint(n, rho, v, yin, sp)) <= TOL64, (route, n, kind)
+    mu = np.linalg.eigvalsh(oracle.laplacian(n, rho, v))
+    gaps = np.diff(mu)
+    if n <= 256 and gaps.min() > 1e-9:
+        tol = max(TOL64, 100 * np.finfo(float).eps * (4 + abs(rho) * float(v @ v)) / gaps.min())
+        _, X = oracle.basis(n, rho, v)
+        assert relerr(y, oracle.forward(X, x)) <= tol, (route, n, kind, tol)
+        assert relerr(xa, oracle.adjoint(X, yin)) <= tol, (route, n, kind, tol)
 
 
 @pytest.mark.parametrize("route", ["dense", "gft"])
