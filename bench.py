@@ -25,6 +25,38 @@ METRIC = "signal-samples/s DCT+ fwd+bwd vs dense GFT, n=64 & 4096, FP32, rel err
 HBM_PEAK_GBS = 8000.0
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "dense_stream_n64_hbm_counters.md")
+STREAM_SOURCE = os.path.join(ROOT, "paper_2409_08970_amd", "csrc", "dense.hip")
+
+
+def kernel_source_hash(path, marker):
+    """sha256 of a kernel's source text: from the line holding `marker` to the
+    next line that is a lone closing brace."""
+    import hashlib
+    lines = open(path).read().splitlines()
+    start = next(i for i, ln in enumerate(lines) if marker in ln)
+    end = next(i for i in range(start, len(lines)) if lines[i] == "}")
+    return hashlib.sha256("\n".join(lines[start:end + 1]).encode()).hexdigest()
+
+
+def measured_traffic(kernel_key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary (FETCH_SIZE
+    and WRITE_SIZE per dispatch, each scaled by what the counter reads for a plain
+    device copy of known size), or None when the kernel's source has changed
+    since the counters were taken."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        rec = json.loads(block)
+        k = rec["kernels"][kernel_key]
+        if kernel_source_hash(STREAM_SOURCE, rec["source_marker"]) != rec["source_sha256"]:
+            return None
+        kib = k["fetch_kib"] * rec["fetch_scale"] + k["write_kib"] * rec["write_scale"]
+        return kib * 1024.0
+    except (OSError, IndexError, KeyError, ValueError, StopIteration):
+        return None
+
+
 def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
@@ -177,7 +209,10 @@ def main():
         "config": {"workload": f"shared-transform batch: n={n}, {batch} AR(0.95) signals, random unit v, "
                                f"rho={W['rho']:.4f}", "route": route, "n": n, "batch": batch},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("k_dense_stream<64, 2>" if best == "f32split" else
+                                                 "k_dense_stream<64, 0>"),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "kernel": "k_dense_stream<64> (forward and adjoint launches)", "avg_launch_ms": launch_ms,
                      "algorithmic_bytes_per_launch": alg_bytes},
         "forward_ms": f_ms, "adjoint_ms": a_ms,

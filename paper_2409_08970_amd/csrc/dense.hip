@@ -243,11 +243,16 @@ __global__ void __launch_bounds__(256) k_dense_small(const float *__restrict__ i
 // ---------------------------------------------------------------------------
 // Streaming kernel for 16 <= N <= 64: each wave owns tiles of 16 signals and
 // computes Y^T = A X^T with v_mfma_f32_16x16x4_f32 (or 16x16x32 BF16), with
-// A = P (forward) or P^T (adjoint) held in VGPRs for the whole launch.  The
-// contraction index k is ordered so that a lane's B fragment is N/4
-// consecutive samples of one signal (float4 loads) and its D fragment is four
-// consecutive outputs of one signal (float4 stores): no LDS, no barriers, and
-// the next tile is loaded while the current one is multiplied.
+// A = P (forward) or P^T (adjoint).  The A operands are built once per
+// workgroup into LDS in lane order (one conflict-free 16-byte read per lane and
+// MFMA step), which keeps the VGPR budget small enough for several waves per
+// SIMD; each wave keeps kDepth tiles of signals in flight in registers (a ring
+// of loads issued kDepth tiles ahead).  The contraction index k is ordered so
+// that a lane's B fragment is N/16 float4 chunks of one signal, interleaved
+// with the three other lanes of that signal (64 contiguous bytes per signal and
+// load instruction), and its D fragment four consecutive outputs of one signal
+// (float4 stores).  Workgroups are persistent: the grid is the resident capacity and
+// tiles are taken in grid-stride order.
 // ---------------------------------------------------------------------------
 // Three-piece BF16 split of an FP32 value: x = h + m + l to within 2^-24 |x|.
 __device__ __forceinline__ void split3(float x, uint16_t &h, uint16_t &m, uint16_t &l) {
@@ -258,124 +263,175 @@ __device__ __forceinline__ void split3(float x, uint16_t &h, uint16_t &m, uint16
     l = f2bf(r2);
 }
 
+template <int N>
+struct StreamCfg {
+    static constexpr int KQ = N / 4;                 // samples per lane and tile
+    static constexpr int CT = N / 16;                // output tiles of 16
+    static constexpr int V4 = KQ / 4;                // float4 per lane and tile
+    static constexpr int kDepth = (N == 64) ? 3 : 4; // tiles in flight per wave
+};
+
+// LDS bytes of the A operands: MODE 0: CT * KQ fragments of 64 floats;
+// MODE 1: CT * KQ/8 fragments of 64 x 8 BF16; MODE 2: three such sets.
+template <int N, int MODE>
+constexpr int stream_lds_bytes() {
+    return MODE == 0 ? StreamCfg<N>::CT * StreamCfg<N>::KQ * 64 * 4
+                     : (MODE == 1 ? 1 : 3) * StreamCfg<N>::CT * (StreamCfg<N>::KQ / 8) * 64 * 16;
+}
+
 // MODE 0: FP32 MFMA.  MODE 1: BF16 operands.  MODE 2: FP32-accurate products from
 // three-piece BF16 splits of both operands, keeping the six cross products of
-// order <= 2^-16 (hh, hm, mh, hl, lh, mm), all accumulated in FP32.
+// order >= 2^-16 (hh, hm, mh, mm, hl, lh) with FP32 accumulation.
 template <int N, int MODE>
-__global__ void __launch_bounds__(256) k_dense_stream(const float *__restrict__ in, float *__restrict__ out,
+__global__ void __launch_bounds__(256, 4) k_dense_stream(const float *__restrict__ in, float *__restrict__ out,
                                                       int64_t batch, const float *__restrict__ P32,
                                                       const uint16_t *__restrict__ P16, int adj) {
-    constexpr bool BF16 = (MODE == 1);
-    constexpr int KQ = N / 4;      // samples per lane and tile (contiguous)
-    constexpr int CT = N / 16;     // output tiles of 16
-    constexpr int V4 = KQ / 4;     // float4 per lane and tile
-    const int lane = threadIdx.x & 63;
+    using C = StreamCfg<N>;
+    constexpr int KQ = C::KQ, CT = C::CT, V4 = C::V4, D = C::kDepth;
+    constexpr int NS = CT * (KQ / 8);                // BF16 fragments per piece
+    __shared__ __align__(16) unsigned char sa[stream_lds_bytes<N, MODE>()];
+    const int tid = threadIdx.x, lane = tid & 63;
     const int l16 = lane & 15, g = lane >> 4;
-    // A fragments: a[c][q] = A[16c + l16][KQ g + q],  A = P (forward) or P^T (adjoint)
-    constexpr int NA = (MODE == 2) ? 1 : CT * KQ;
-    constexpr int NS = (MODE == 2) ? CT * (KQ / 8) : 1;
-    float a[CT][(MODE == 2) ? 1 : KQ];
-    bf8 ah[NS], am[NS], al[NS];
-    (void)NA;
-#pragma unroll
-    for (int c = 0; c < CT; ++c)
-#pragma unroll
-        for (int q = 0; q < KQ; ++q) {
-            const int row = 16 * c + l16, col = KQ * g + q;
-            if constexpr (MODE == 2) {
-                const float pv = adj ? P32[(size_t)col * N + row] : P32[(size_t)row * N + col];
-                uint16_t h, m, l;
-                split3(pv, h, m, l);
-                ah[c * (KQ / 8) + q / 8][q % 8] = bits2bf(h);
-                am[c * (KQ / 8) + q / 8][q % 8] = bits2bf(m);
-                al[c * (KQ / 8) + q / 8][q % 8] = bits2bf(l);
-            } else if constexpr (BF16) {
-                const uint16_t h = adj ? P16[(size_t)col * N + row] : P16[(size_t)row * N + col];
-                a[c][q] = __uint_as_float((uint32_t)h << 16);
-            } else {
-                a[c][q] = adj ? P32[(size_t)col * N + row] : P32[(size_t)row * N + col];
-            }
-        }
-    const int64_t ntiles = (batch + 15) / 16;
+    // Full tiles (16 valid signals) run branch-free: prefetch addresses are
+    // clamped to the last full tile, so every load is issued unconditionally and
+    // the wait counts stay exact (a guarded load makes the compiler wait for all
+    // outstanding loads).  A ragged last tile is handled once at the end.
+    const int64_t nfull = batch / 16;
     const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    auto load = [&](int64_t tile, float4 *b) {
-        const int64_t sig = tile * 16 + l16;
-        if (tile < ntiles && sig < batch) {
-            const float4 *src = reinterpret_cast<const float4 *>(in + sig * N + KQ * g);
+    // float4 number v of a lane is chunk 4 v + g of its signal's row, so the four
+    // lanes of a signal read 64 contiguous bytes per load instruction
+    auto loadc = [&](int64_t tile, f4 *b) {
+        const int64_t t = tile < nfull ? tile : nfull - 1;
+        const f4 *src = reinterpret_cast<const f4 *>(in + (t * 16 + l16) * N);
 #pragma unroll
-            for (int v = 0; v < V4; ++v) b[v] = src[v];
-        } else {
-#pragma unroll
-            for (int v = 0; v < V4; ++v) b[v] = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
+        for (int v = 0; v < V4; ++v) b[v] = src[4 * v + g];
     };
-    float4 bcur[V4], bnext[V4];
-    load(wave0, bcur);
-    for (int64_t tile = wave0; tile < ntiles; tile += nwaves) {
-        load(tile + nwaves, bnext);
+    // the first kDepth tiles are requested before the A operands are built
+    f4 ring[D][V4];
+    if (nfull > 0) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) loadc(wave0 + d * nwaves, ring[d]);
+    }
+    // A operands into LDS in lane order.  Lane (l16, g) holds sample
+    // sigma(q, g) = 16 (q / 4) + 4 g + q % 4 of its signal as its q-th B value.
+    auto sigma = [](int q, int gg) -> int { return 16 * (q >> 2) + 4 * gg + (q & 3); };
+    auto aval = [&](int row, int col) -> float {
+        return adj ? P32[(size_t)col * N + row] : P32[(size_t)row * N + col];
+    };
+    if constexpr (MODE == 0) {
+        float *af = reinterpret_cast<float *>(sa);    // [CT][KQ/4][64 lanes][4]
+        for (int e = tid; e < CT * KQ * 64; e += blockDim.x) {
+            const int q4 = e & 3, ln = (e >> 2) & 63, rest = e >> 8;   // rest = c * (KQ/4) + qq
+            const int c = rest / (KQ / 4), qq = rest % (KQ / 4);
+            const int q = 4 * qq + q4;
+            af[e] = aval(16 * c + (ln & 15), sigma(q, ln >> 4));
+        }
+    } else {
+        uint16_t *af = reinterpret_cast<uint16_t *>(sa);  // [piece][NS][64 lanes][8]
+        for (int e = tid; e < NS * 64 * 8; e += blockDim.x) {
+            const int el = e & 7, ln = (e >> 3) & 63, f = e >> 9;      // f = c * (KQ/8) + st
+            const int c = f / (KQ / 8), st = f % (KQ / 8);
+            const int row = 16 * c + (ln & 15), col = sigma(8 * st + el, ln >> 4);
+            if constexpr (MODE == 1) {
+                af[e] = adj ? P16[(size_t)col * N + row] : P16[(size_t)row * N + col];
+            } else {
+                uint16_t h, m, l;
+                split3(aval(row, col), h, m, l);
+                af[e] = h;
+                af[NS * 512 + e] = m;
+                af[2 * NS * 512 + e] = l;
+            }
+        }
+    }
+    __syncthreads();
+
+    auto compute_store = [&](int64_t tile, const f4 *bt, bool guarded) {
+        // an opaque copy of the lane index keeps the LDS operand reads inside the
+        // tile loop (hoisted, they would pin all of A in VGPRs)
+        int la = lane;
+        asm volatile("" : "+v"(la));
         f4 acc[CT];
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[c] = f4{0.f, 0.f, 0.f, 0.f};
-        const float *b = reinterpret_cast<const float *>(bcur);
-        if constexpr (MODE == 2) {
+        const float *b = reinterpret_cast<const float *>(bt);
+        if constexpr (MODE == 0) {
+            const float4 *af = reinterpret_cast<const float4 *>(sa);
+#pragma unroll
+            for (int qq = 0; qq < KQ / 4; ++qq)
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    const float4 a4 = af[(c * (KQ / 4) + qq) * 64 + la];
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.x, b[4 * qq + 0], acc[c], 0, 0, 0);
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.y, b[4 * qq + 1], acc[c], 0, 0, 0);
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.z, b[4 * qq + 2], acc[c], 0, 0, 0);
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.w, b[4 * qq + 3], acc[c], 0, 0, 0);
+                }
+        } else {
+            const bf8 *af = reinterpret_cast<const bf8 *>(sa);
 #pragma unroll
             for (int st = 0; st < KQ / 8; ++st) {
                 bf8 bh, bm, bl;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    uint16_t h, m, l;
-                    split3(b[8 * st + e], h, m, l);
-                    bh[e] = bits2bf(h);
-                    bm[e] = bits2bf(m);
-                    bl[e] = bits2bf(l);
+                    if constexpr (MODE == 2) {
+                        uint16_t h, m, l;
+                        split3(b[8 * st + e], h, m, l);
+                        bh[e] = bits2bf(h);
+                        bm[e] = bits2bf(m);
+                        bl[e] = bits2bf(l);
+                    } else {
+                        bh[e] = bits2bf(f2bf(b[8 * st + e]));
+                    }
                 }
 #pragma unroll
                 for (int c = 0; c < CT; ++c) {
-                    const int i = c * (KQ / 8) + st;
-                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[c], 0, 0, 0);
-                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[c], 0, 0, 0);
-                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[i], bm, acc[c], 0, 0, 0);
-                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[i], bh, acc[c], 0, 0, 0);
-                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bm, acc[c], 0, 0, 0);
-                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[c], 0, 0, 0);
-                }
-            }
-        } else if constexpr (!BF16) {
-#pragma unroll
-            for (int q = 0; q < KQ; ++q)
-#pragma unroll
-                for (int c = 0; c < CT; ++c)
-                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c][q], b[q], acc[c], 0, 0, 0);
-        } else {
-#pragma unroll
-            for (int st = 0; st < KQ / 8; ++st) {
-                bf8 bv;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) bv[e] = bits2bf(f2bf(b[8 * st + e]));
-#pragma unroll
-                for (int c = 0; c < CT; ++c) {
-                    bf8 av;
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) av[e] = bits2bf((uint16_t)(__float_as_uint(a[c][8 * st + e]) >> 16));
-                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[c], 0, 0, 0);
+                    const int f = c * (KQ / 8) + st;
+                    const bf8 ah = af[f * 64 + la];
+                    if constexpr (MODE == 2) {
+                        const bf8 am = af[(NS + f) * 64 + la];
+                        const bf8 al = af[(2 * NS + f) * 64 + la];
+                        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[c], 0, 0, 0);
+                        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[c], 0, 0, 0);
+                        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, acc[c], 0, 0, 0);
+                        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, acc[c], 0, 0, 0);
+                        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, acc[c], 0, 0, 0);
+                    }
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[c], 0, 0, 0);
                 }
             }
         }
         const int64_t sig = tile * 16 + l16;
-        if (sig < batch) {
-            float4 *dst = reinterpret_cast<float4 *>(out + sig * N + 4 * g);
+        if (!guarded || sig < batch) {
+            f4 *dst = reinterpret_cast<f4 *>(out + sig * N + 4 * g);
 #pragma unroll
-            for (int c = 0; c < CT; ++c) dst[4 * c] = make_float4(acc[c][0], acc[c][1], acc[c][2], acc[c][3]);
+            for (int c = 0; c < CT; ++c) dst[4 * c] = acc[c];
+        }
+    };
+    if (nfull > 0) {
+        int64_t base = wave0;
+        for (; base + (D - 1) * nwaves < nfull; base += D * nwaves) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                compute_store(base + d * nwaves, ring[d], false);
+                loadc(base + (d + D) * nwaves, ring[d]);
+            }
         }
 #pragma unroll
-        for (int v = 0; v < V4; ++v) bcur[v] = bnext[v];
+        for (int d = 0; d < D - 1; ++d)
+            if (base + d * nwaves < nfull) compute_store(base + d * nwaves, ring[d], false);
+    }
+    if (nfull * 16 < batch && wave0 == nfull % nwaves) {
+        // the ragged last tile: guarded loads (zeros past the batch) and stores
+        const int64_t sig = nfull * 16 + l16;
+        f4 b[V4];
+        const f4 *src = reinterpret_cast<const f4 *>(in + sig * N);
+#pragma unroll
+        for (int v = 0; v < V4; ++v) b[v] = (sig < batch) ? src[4 * v + g] : f4{0.f, 0.f, 0.f, 0.f};
+        compute_store(nfull, b, true);
     }
 }
 
-// ---------------------------------------------------------------------------
-// Tiny n (4, 8): one thread per signal, P and the DCT matrix from LDS.
-// ---------------------------------------------------------------------------
 template <int N>
 __global__ void __launch_bounds__(256) k_dense_tiny(const float *__restrict__ in, float *__restrict__ out, int64_t batch,
                              const float *__restrict__ P32, const cplx<float> *__restrict__ tw, int adj,
@@ -596,17 +652,38 @@ __global__ void __launch_bounds__(256) k_gemm64(const double *__restrict__ A, co
             }
 }
 
-int persistent_blocks(int64_t nchunks) {
+int num_cus() {
     static int ncu = 0;
     if (ncu == 0) {
-        int dev = 0;
+        int dev = 0, v = 0;
         hipGetDevice(&dev);
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
-        if (ncu <= 0) ncu = 256;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
+        else ncu = 256;
     }
-    const int64_t cap = (int64_t)ncu * 4;
+    return ncu;
+}
+
+int persistent_blocks(int64_t nchunks) {
+    const int64_t cap = (int64_t)num_cus() * 4;
     return (int)(nchunks < cap ? nchunks : cap);
+}
+
+// Grid of the streaming kernel: every workgroup resident at once (the kernel
+// strides over tiles), never more workgroups than groups of four tiles.
+template <int N, int MODE>
+int stream_blocks(int64_t ntiles) {
+    static int cap = 0;
+    if (cap == 0) {
+        int per = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_dense_stream<N, MODE>, 256, 0) != hipSuccess ||
+            per <= 0) {
+            (void)hipGetLastError();
+            per = 2;
+        }
+        cap = per * num_cus();
+    }
+    const int64_t want = (ntiles + 3) / 4;
+    return (int)(want < cap ? want : cap);
 }
 
 template <int N, bool BF>
@@ -712,14 +789,11 @@ dctplus_status dense_apply(dctplus_plan_s *p, const void *inv, void *outv, int64
             }
         } else {
             const int64_t ntiles = (batch + 15) / 16;
-            const int64_t waves_wanted = ntiles;
-            int blocks = (int)((waves_wanted + 3) / 4);
-            const int cap = persistent_blocks(1 << 30) * 2;   // 8 blocks (32 waves) per CU
-            if (blocks > cap) blocks = cap;
             const float *P32 = p->t.mt32;
             const uint16_t *P16 = p->t.mt16;
-#define DCTPLUS_STREAM(NN, MM) \
-    hipLaunchKernelGGL((k_dense_stream<NN, MM>), dim3(blocks), dim3(256), 0, s, in, out, batch, P32, P16, adj)
+#define DCTPLUS_STREAM(NN, MM)                                                                             \
+    hipLaunchKernelGGL((k_dense_stream<NN, MM>), dim3(stream_blocks<NN, MM>(ntiles)), dim3(256), 0, s, in, out, \
+                       batch, P32, P16, adj)
             if (split) {
                 if (n == 32) DCTPLUS_STREAM(32, 2);
                 else DCTPLUS_STREAM(64, 2);
