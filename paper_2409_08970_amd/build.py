@@ -15,6 +15,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result", f"-I{INCLUDE}",
 ]
+# the FP32 dense product for n > 64 is a plain GEMM and goes to hipBLASLt
+LIBS = ["-L/opt/rocm/lib", "-lhipblaslt"]
 
 
 def sources():
@@ -24,7 +26,7 @@ def sources():
 def build(verbose: bool = False) -> str:
     """Compile every HIP source into one shared library (always recompiles)."""
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", *FLAGS, "-o", tmp, *sources()]
+    cmd = ["hipcc", *FLAGS, "-o", tmp, *sources(), *LIBS]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -70,6 +70,7 @@ struct dctplus_plan_s {
     size_t dev_bytes;
     void *work;               // lazily grown workspace (FFT scratch for large n, gradient)
     size_t work_bytes;
+    void *blas;               // hipBLASLt set-up of the FP32 dense product for n > 64 (plain GEMM)
     dctplus::PlanTables t;
 };
 
@@ -84,6 +85,7 @@ dctplus_status fast_apply(dctplus_plan_s *p, const void *in, void *out, int64_t 
 dctplus_status dense_apply(dctplus_plan_s *p, const void *in, void *out, int64_t batch, bool adjoint,
                            hipStream_t s);
 dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s);
+void dense_release(dctplus_plan_s *p);
 dctplus_status grad_apply(dctplus_plan_s *p, const float *y, const float *gy, int64_t batch, float *gx,
                           double *grho, double *gv, hipStream_t s);
 dctplus_status plan_build(dctplus_plan_s *p, const double *v_host, hipStream_t s);

@@ -13,6 +13,10 @@
 // wave multiplies 16 of them by P, whose B fragments stay in VGPRs for the
 // whole persistent loop.  For n >= 128 a tiled GEMM with P staged through LDS
 // is used, with the DCT as a separate pass.
+#include <hipblaslt/hipblaslt.h>
+
+#include <new>
+
 #include "fft.h"
 
 namespace dctplus {
@@ -537,59 +541,6 @@ __global__ void __launch_bounds__(256) k_dct_rows(PlanTables t, const float *__r
 
 constexpr int TBM = 64, TBN = 64, TBK = 16;
 
-__global__ void __launch_bounds__(256) k_gemm(const float *__restrict__ A, const float *__restrict__ P,
-                                              float *__restrict__ C, int64_t batch, int n, int transB) {
-    // B[k][j] = transB ? P[j][k] : P[k][j]
-    __shared__ float As[TBM][TBK + 1];
-    __shared__ float Bs[TBK][TBN + 1];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int l16 = lane & 15, lq = lane >> 4;
-    const int64_t m0 = (int64_t)blockIdx.y * TBM;
-    const int n0 = blockIdx.x * TBN;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;   // 2x2 waves, 32x32 each
-    f4 acc[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < n; k0 += TBK) {
-        for (int e = tid; e < TBM * TBK; e += 256) {
-            const int r = e / TBK, k = e % TBK;
-            const int64_t row = m0 + r;
-            As[r][k] = row < batch ? A[row * n + k0 + k] : 0.0f;
-        }
-        for (int e = tid; e < TBK * TBN; e += 256) {
-            int k, j;
-            if (transB) { j = e / TBK; k = e % TBK; }
-            else { k = e / TBN; j = e % TBN; }
-            Bs[k][j] = transB ? P[(size_t)(n0 + j) * n + k0 + k] : P[(size_t)(k0 + k) * n + n0 + j];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int s = 0; s < TBK / 4; ++s) {
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                const float av = As[wm + 16 * a + l16][4 * s + lq];
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const float bv = Bs[4 * s + lq][wn + 16 * b + l16];
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[a][b], 0, 0, 0);
-                }
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t row = m0 + wm + 16 * a + 4 * lq + v;
-                if (row < batch) C[row * n + n0 + wn + 16 * b + l16] = acc[a][b][v];
-            }
-}
-
 // FP64 product for FP64 plans, any n >= 4: C[b][j] = sum_k A[b][k] B[k][j] with
 // B[k][j] = P[j][k] (transB, forward y = P x) or P[k][j] (adjoint x = P^T y).
 // 64 x 64 output tiles, 2 x 2 waves of 32 x 32 on 16x16x4 FP64 MFMA, k-steps of
@@ -652,6 +603,99 @@ __global__ void __launch_bounds__(256) k_gemm64(const double *__restrict__ A, co
             }
 }
 
+// FP32 dense product for n > 64: a plain GEMM, run by hipBLASLt.  One handle,
+// two matmul descriptors (forward: D = P X, adjoint: D = P^T Y in column-major
+// terms) and, per direction, the layouts and algorithm of the last batch size.
+struct BlasLtPlan {
+    hipblasLtHandle_t h = nullptr;
+    hipblasLtMatmulDesc_t desc[2] = {nullptr, nullptr};
+    hipblasLtMatmulPreference_t pref = nullptr;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    struct Cached {
+        int64_t batch = -1;
+        hipblasLtMatrixLayout_t a = nullptr, b = nullptr, d = nullptr;
+        hipblasLtMatmulAlgo_t algo;
+    } c[2];
+};
+
+void blaslt_release(BlasLtPlan *b) {
+    if (!b) return;
+    for (auto &c : b->c) {
+        if (c.a) hipblasLtMatrixLayoutDestroy(c.a);
+        if (c.b) hipblasLtMatrixLayoutDestroy(c.b);
+        if (c.d) hipblasLtMatrixLayoutDestroy(c.d);
+    }
+    for (auto d : b->desc)
+        if (d) hipblasLtMatmulDescDestroy(d);
+    if (b->pref) hipblasLtMatmulPreferenceDestroy(b->pref);
+    if (b->h) hipblasLtDestroy(b->h);
+    if (b->ws) (void)hipFree(b->ws);
+    delete b;
+}
+
+dctplus_status blaslt_create(int n, BlasLtPlan **out) {
+    BlasLtPlan *b = new (std::nothrow) BlasLtPlan();
+    if (!b) return fail(DCTPLUS_ENOMEM, "host allocation failed");
+    b->ws_bytes = size_t(32) << 20;
+    bool ok = hipMalloc(&b->ws, b->ws_bytes) == hipSuccess;
+    if (!ok) {
+        b->ws = nullptr;
+        (void)hipGetLastError();
+        blaslt_release(b);
+        return fail(DCTPLUS_ENOMEM, "hipMalloc for the GEMM workspace failed");
+    }
+    ok = hipblasLtCreate(&b->h) == HIPBLAS_STATUS_SUCCESS;
+    const int32_t ops[2][2] = {{HIPBLAS_OP_T, HIPBLAS_OP_N}, {HIPBLAS_OP_N, HIPBLAS_OP_N}};
+    for (int d = 0; ok && d < 2; ++d) {
+        ok = hipblasLtMatmulDescCreate(&b->desc[d], HIPBLAS_COMPUTE_32F, HIP_R_32F) == HIPBLAS_STATUS_SUCCESS &&
+             hipblasLtMatmulDescSetAttribute(b->desc[d], HIPBLASLT_MATMUL_DESC_TRANSA, &ops[d][0], sizeof(int32_t)) ==
+                 HIPBLAS_STATUS_SUCCESS &&
+             hipblasLtMatmulDescSetAttribute(b->desc[d], HIPBLASLT_MATMUL_DESC_TRANSB, &ops[d][1], sizeof(int32_t)) ==
+                 HIPBLAS_STATUS_SUCCESS;
+    }
+    const uint64_t wsb = b->ws_bytes;
+    ok = ok && hipblasLtMatmulPreferenceCreate(&b->pref) == HIPBLAS_STATUS_SUCCESS &&
+         hipblasLtMatmulPreferenceSetAttribute(b->pref, HIPBLASLT_MATMUL_PREF_MAX_WORKSPACE_BYTES, &wsb, sizeof(wsb)) ==
+             HIPBLAS_STATUS_SUCCESS;
+    if (!ok) {
+        blaslt_release(b);
+        return fail(DCTPLUS_EDEVICE, "hipBLASLt set-up failed for n = %d", n);
+    }
+    *out = b;
+    return DCTPLUS_OK;
+}
+
+// D (n x batch, column-major, ld n) = op(P^c) S with P^c the row-major factor read column-major.
+dctplus_status blaslt_apply(BlasLtPlan *b, int n, int64_t batch, int dir, const float *P, const float *S, float *D,
+                            hipStream_t s) {
+    auto &c = b->c[dir];
+    if (c.batch != batch) {
+        for (auto *l : {&c.a, &c.b, &c.d})
+            if (*l) {
+                hipblasLtMatrixLayoutDestroy(*l);
+                *l = nullptr;
+            }
+        c.batch = -1;
+        bool ok = hipblasLtMatrixLayoutCreate(&c.a, HIP_R_32F, n, n, n) == HIPBLAS_STATUS_SUCCESS &&
+                  hipblasLtMatrixLayoutCreate(&c.b, HIP_R_32F, n, (uint64_t)batch, n) == HIPBLAS_STATUS_SUCCESS &&
+                  hipblasLtMatrixLayoutCreate(&c.d, HIP_R_32F, n, (uint64_t)batch, n) == HIPBLAS_STATUS_SUCCESS;
+        hipblasLtMatmulHeuristicResult_t res[1];
+        int found = 0;
+        ok = ok && hipblasLtMatmulAlgoGetHeuristic(b->h, b->desc[dir], c.a, c.b, c.d, c.d, b->pref, 1, res, &found) ==
+                       HIPBLAS_STATUS_SUCCESS &&
+             found > 0 && res[0].workspaceSize <= b->ws_bytes;
+        if (!ok) return fail(DCTPLUS_EDEVICE, "hipBLASLt has no algorithm for n = %d, batch = %lld", n, (long long)batch);
+        c.algo = res[0].algo;
+        c.batch = batch;
+    }
+    const float one = 1.0f, zero = 0.0f;
+    if (hipblasLtMatmul(b->h, b->desc[dir], &one, P, c.a, S, c.b, &zero, D, c.d, D, c.d, &c.algo, b->ws, b->ws_bytes,
+                        s) != HIPBLAS_STATUS_SUCCESS)
+        return fail(DCTPLUS_EDEVICE, "hipblasLtMatmul failed");
+    return DCTPLUS_OK;
+}
+
 int num_cus() {
     static int ncu = 0;
     if (ncu == 0) {
@@ -698,6 +742,11 @@ void launch_small(const dctplus_plan_s *p, const float *in, float *out, int64_t 
 
 }  // namespace
 
+void dense_release(dctplus_plan_s *p) {
+    blaslt_release((BlasLtPlan *)p->blas);
+    p->blas = nullptr;
+}
+
 dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s) {
     const int n = (int)p->n;
     const size_t elems = (size_t)n * n;
@@ -723,6 +772,13 @@ dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s) {
         p->t.mt32 = nullptr;
         (void)hipGetLastError();
         return fail(DCTPLUS_ENOMEM, "hipMalloc for the %d x %d dense factor failed", n, n);
+    }
+    if (n > 64 && p->dtype == DCTPLUS_F32) {
+        // above n = 64 the FP32 dense product is a plain GEMM: the platform library runs it
+        BlasLtPlan *b = nullptr;
+        dctplus_status st = blaslt_create(n, &b);
+        if (st != DCTPLUS_OK) return st;
+        p->blas = b;
     }
     if (p->dtype == DCTPLUS_BF16) {
         e = hipMalloc(&p->t.mt16, sizeof(uint16_t) * elems);
@@ -818,19 +874,26 @@ dctplus_status dense_apply(dctplus_plan_s *p, const void *inv, void *outv, int64
         const int nsig = n >= 4096 ? 1 : 4096 / n;
         const size_t lds = sizeof(cplx<float>) * (size_t)nsig * (n / 2);
         const dim3 dgrid((unsigned)((batch + nsig - 1) / nsig));
-        const dim3 ggrid(n / TBN, (unsigned)((batch + TBM - 1) / TBM));
+        if (batch > INT32_MAX) return fail(DCTPLUS_EINVAL, "batch too large for the dense product");
+        BlasLtPlan *b = (BlasLtPlan *)p->blas;
+        if (!b) return fail(DCTPLUS_EDEVICE, "no GEMM set-up on this plan");
+        // row-major [batch, n] arrays are column-major n x batch with ld n; the
+        // row-major factor P (row i = output i) read column-major is P^T
+        dctplus_status st;
         if (!adjoint) {
             const float *A = in;
             if (pre) {
                 hipLaunchKernelGGL(k_dct_rows, dgrid, dim3(256), lds, s, p->t, in, tmp, batch, 0, nsig);
                 A = tmp;
             }
-            hipLaunchKernelGGL(k_gemm, ggrid, dim3(256), 0, s, A, (const float *)p->t.mt32, out, batch, n, 1);
+            st = blaslt_apply(b, n, batch, 0, p->t.mt32, A, out, s);     // y_b = P x_b
         } else {
             float *C = pre ? tmp : out;
-            hipLaunchKernelGGL(k_gemm, ggrid, dim3(256), 0, s, in, (const float *)p->t.mt32, C, batch, n, 0);
-            if (pre) hipLaunchKernelGGL(k_dct_rows, dgrid, dim3(256), lds, s, p->t, tmp, out, batch, 1, nsig);
+            st = blaslt_apply(b, n, batch, 1, p->t.mt32, in, C, s);      // x_b = P^T y_b
+            if (st == DCTPLUS_OK && pre)
+                hipLaunchKernelGGL(k_dct_rows, dgrid, dim3(256), lds, s, p->t, tmp, out, batch, 1, nsig);
         }
+        if (st != DCTPLUS_OK) return st;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "dense route launch");
