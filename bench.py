@@ -150,6 +150,41 @@ def bench_selection(torch, dev, steps, warmup):
                          "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": bytes_}}
 
 
+def bench_gradient(torch, dev, steps, warmup):
+    """Gradient workload: n = 256, 65,536 N(0,1) signals, rho = 1, random unit v,
+    loss = mean |y|.  A step = forward + gradient (dl/dx via the adjoint, dl/drho
+    and dl/dv via the batch Gram matrix), inputs resident in HBM."""
+    import workloads
+    from paper_2409_08970_amd import Plan
+    W = workloads.workload5()
+    n, batch = W["n"], W["x"].shape[0]
+    x = torch.from_numpy(W["x"]).to(dev)
+    pl = Plan(n, W["rho"], W["v"], route="auto")
+    y = torch.empty_like(x)
+
+    def step():
+        pl.forward(x, out=y)
+        gy = torch.sign(y) / y.numel()
+        pl.grad(y, gy)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    a, b = _events(torch)
+    reps = max(5, steps)
+    a.record()
+    for _ in range(reps):
+        step()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    pl.close()
+    return {"workload": f"n={n}, {batch} N(0,1) signals, rho={W['rho']}, random unit v, loss mean|y|",
+            "ms_per_step": ms, "signal_samples_per_s": batch * n / (ms * 1e-3),
+            "step": "forward + dl/dx (adjoint) + dl/drho, dl/dv (Gram matrix G = sum gy y^T, 2 B n^2 flops)",
+            "gram_tflops_if_alone": 2.0 * batch * n * n / (ms * 1e-3) / 1e12}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,6 +304,8 @@ def main():
     if not args.no_extra:
         result["selection"] = bench_selection(torch, dev, args.steps, args.warmup)
         print("selection", result["selection"], file=sys.stderr, flush=True)
+        result["gradient"] = bench_gradient(torch, dev, args.steps, args.warmup)
+        print("gradient", result["gradient"], file=sys.stderr, flush=True)
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(W, args.cpu_sample)

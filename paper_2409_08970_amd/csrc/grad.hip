@@ -80,32 +80,74 @@ __device__ __forceinline__ double wcoef(const PlanTables &t, int i) {
     return t.a[i] / t.rho;
 }
 
-// r_i = sum_k (G_ik - G_ki) / (mu_i - mu_k) w_k ,  q_i = w_i sum_k G_ik w_k / (mu_i - mu_k)
-__global__ void k_grad_vec(PlanTables t, const float *__restrict__ partial, int nsplit, double *__restrict__ rvec,
-                           double *__restrict__ qvec) {
+// G = sum of the split-K partials, in FP64 and in a fixed order; written as
+// G (row-major) and G^T so that both are read along rows below.
+__global__ void __launch_bounds__(256) k_gram_sum(const float *__restrict__ partial, int nsplit, int n,
+                                                  double *__restrict__ G, double *__restrict__ GT) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nn = (int64_t)n * n;
+    if (e >= nn) return;
+    double g = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) g += (double)partial[(size_t)sp * nn + e];
+    const int i = (int)(e / n), k = (int)(e % n);
+    G[e] = g;
+    GT[(size_t)k * n + i] = g;
+}
+
+// r_i = sum_k (G_ik - G_ki) / (mu_i - mu_k) w_k ,  q_i = w_i sum_k G_ik w_k / (mu_i - mu_k);
+// one wave per i, lanes over k.
+__global__ void __launch_bounds__(256) k_grad_vec(PlanTables t, const double *__restrict__ G,
+                                                  const double *__restrict__ GT, double *__restrict__ rvec,
+                                                  double *__restrict__ qvec) {
     const int n = t.n;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double mui = t.mu[i], wi = wcoef(t, i);
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (i >= n) return;   // the whole wave leaves
+    const double mui = t.mu[i];
     double r = 0.0, q = 0.0;
-    for (int k = 0; k < n; ++k) {
+    for (int k = lane; k < n; k += 64) {
         if (k == i) continue;
-        double gik = 0.0, gki = 0.0;
-        for (int sp = 0; sp < nsplit; ++sp) {
-            gik += (double)partial[(size_t)sp * n * n + (size_t)i * n + k];
-            gki += (double)partial[(size_t)sp * n * n + (size_t)k * n + i];
-        }
+        const double gik = G[(size_t)i * n + k], gki = GT[(size_t)i * n + k];
         const double inv = 1.0 / (mui - t.mu[k]);
         const double wk = wcoef(t, k);
         r += (gik - gki) * inv * wk;
         q += gik * inv * wk;
     }
-    rvec[i] = r;
-    qvec[i] = q * wi;
+    r = wave_sum(r);
+    q = wave_sum(q);
+    if (lane == 0) {
+        rvec[i] = r;
+        qvec[i] = q * wcoef(t, i);
+    }
 }
 
 // dl/drho = sum_i q_i ; dl/dv = rho X r  (FP64: Cauchy transpose, then DCT-III)
-__global__ void __launch_bounds__(256) k_grad_final(PlanTables t, const double *__restrict__ rvec,
+// s_j = sum_i M_ij r_i (M = diag(a) C(mu, lambda) diag(z), deflated rows e_o);
+// one wave per j, lanes over i.
+__global__ void __launch_bounds__(256) k_grad_s(PlanTables t, const double *__restrict__ rvec,
+                                                double *__restrict__ svec) {
+    const int n = t.n;
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (j >= n) return;   // the whole wave leaves
+    const double zj = t.z[j];
+    double s = 0.0;
+    for (int i = lane; i < n; i += 64) {
+        const int kind = t.kind[i], o = t.origin[i];
+        if (kind == ROW_DEFLATED) {
+            if (o == j) s += rvec[i];
+        } else if (zj != 0.0) {
+            const double sj = (j - o) >= 0 ? t.sintab[j - o] : -t.sintab[o - j];
+            const double d = 4.0 * sj * t.sintab[j + o];
+            s += t.a[i] * zj / (t.tau[i] - d) * rvec[i];
+        }
+    }
+    s = wave_sum(s);
+    if (lane == 0) svec[j] = s;
+}
+
+// dl/drho = sum_i q_i; dl/dv = rho U s (an inverse DCT of s).  One workgroup.
+__global__ void __launch_bounds__(256) k_grad_final(PlanTables t, const double *__restrict__ svec,
                                                     const double *__restrict__ qvec, double *__restrict__ grho,
                                                     double *__restrict__ gv) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -117,22 +159,7 @@ __global__ void __launch_bounds__(256) k_grad_final(PlanTables t, const double *
     for (int i = tid; i < n; i += nthr) acc += qvec[i];
     acc = wave_sum(acc);
     if ((tid & 63) == 0) red[tid >> 6] = acc;
-    // s_j = sum_i M_ij r_i
-    for (int j = tid; j < n; j += nthr) {
-        double s = 0.0;
-        const double zj = t.z[j];
-        for (int i = 0; i < n; ++i) {
-            const int kind = t.kind[i], o = t.origin[i];
-            if (kind == ROW_DEFLATED) {
-                if (o == j) s += rvec[i];
-            } else if (zj != 0.0) {
-                const double sj = (j - o) >= 0 ? t.sintab[j - o] : -t.sintab[o - j];
-                const double d = 4.0 * sj * t.sintab[j + o];
-                s += t.a[i] * zj / (t.tau[i] - d) * rvec[i];
-            }
-        }
-        sdv[j] = s;
-    }
+    for (int j = tid; j < n; j += nthr) sdv[j] = svec[j];
     __syncthreads();
     if (tid == 0 && grho) {
         double s = 0.0;
@@ -174,19 +201,26 @@ dctplus_status grad_apply(dctplus_plan_s *p, const float *y, const float *gy, in
     rows_per = (rows_per + GK - 1) / GK * GK;
     if (rows_per < GK) rows_per = GK;
     const size_t pbytes = (size_t)nsplit * n * n * sizeof(float);
-    const size_t vbytes = 2 * sizeof(double) * n;
+    const size_t gbytes = 2 * sizeof(double) * (size_t)n * n;
+    const size_t vbytes = 3 * sizeof(double) * n;
     // the workspace may already hold a FAST/DENSE scratch from the gx call above,
     // which has completed its use of it in stream order
-    dctplus_status st = ensure_work(p, pbytes + vbytes);
+    dctplus_status st = ensure_work(p, pbytes + gbytes + vbytes);
     if (st != DCTPLUS_OK) return st;
     float *partial = (float *)p->work;
-    double *rvec = (double *)((char *)p->work + pbytes);
+    double *G = (double *)((char *)p->work + pbytes);
+    double *GT = G + (size_t)n * n;
+    double *rvec = GT + (size_t)n * n;
     double *qvec = rvec + n;
+    double *svec = qvec + n;
     hipLaunchKernelGGL(k_gram, dim3(nt, nt, nsplit), dim3(256), 0, s, gy, y, partial, batch, n, rows_per);
-    hipLaunchKernelGGL(k_grad_vec, dim3((n + 255) / 256), dim3(256), 0, s, p->t, (const float *)partial, nsplit,
+    hipLaunchKernelGGL(k_gram_sum, dim3((unsigned)(((size_t)n * n + 255) / 256)), dim3(256), 0, s,
+                       (const float *)partial, nsplit, n, G, GT);
+    hipLaunchKernelGGL(k_grad_vec, dim3((n + 3) / 4), dim3(256), 0, s, p->t, (const double *)G, (const double *)GT,
                        rvec, qvec);
     const size_t lds = sizeof(double) * n + sizeof(cplx<double>) * (n / 2);
-    hipLaunchKernelGGL(k_grad_final, dim3(1), dim3(256), lds, s, p->t, (const double *)rvec, (const double *)qvec,
+    hipLaunchKernelGGL(k_grad_s, dim3((n + 3) / 4), dim3(256), 0, s, p->t, (const double *)rvec, svec);
+    hipLaunchKernelGGL(k_grad_final, dim3(1), dim3(256), lds, s, p->t, (const double *)svec, (const double *)qvec,
                        grho, gv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "gradient launch");

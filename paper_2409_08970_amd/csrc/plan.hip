@@ -155,28 +155,34 @@ struct Secular {
     double F, Fp;   // sum over non-origin poles of z^2 / (d - t) and z^2 / (d - t)^2
 };
 
-__device__ Secular secular_eval(const PlanTables &t, const int32_t *J, int nj, int o, double tt) {
-    Secular s{1.0 / t.rho, 0.0};
-    for (int q = 0; q < nj; ++q) {
+// Secular sums of one root, split over the 64 lanes of a wave (poles q = lane,
+// lane + 64, ...) and reduced with a butterfly, so every lane holds the same sums.
+__device__ __forceinline__ Secular secular_eval_wave(const PlanTables &t, const int32_t *J, int nj, int o,
+                                                     double tt, int lane) {
+    double F = 0.0, Fp = 0.0;
+    for (int q = lane; q < nj; q += 64) {
         const int j = J[q];
         if (j == o) continue;
         const double zj = t.z[j];
         const double den = lam_diff(t.sintab, t.n, j, o) - tt;
         const double r = zj / den;
-        s.F += zj * r;
-        s.Fp += r * r;
+        F += zj * r;
+        Fp += r * r;
     }
-    return s;
+    return Secular{1.0 / t.rho + wave_sum(F), wave_sum(Fp)};
 }
 
-// One thread per secular root.  Safeguarded Newton on g(t) = z_o^2 - t F(t)
+// One wave per secular root.  Safeguarded Newton on g(t) = z_o^2 - t F(t)
 // (the secular function times -t, which removes the pole at the origin), with
-// a bisection bracket kept from the sign of the secular function itself.
-__global__ void k_roots(PlanTables t, const int32_t *__restrict__ J, const double *__restrict__ misc,
-                        int32_t *__restrict__ r_o, double *__restrict__ r_tau, double *__restrict__ r_a) {
+// a bisection bracket kept from the sign of the secular function itself.  All
+// control flow is uniform across the wave (the sums are identical on every lane).
+__global__ void __launch_bounds__(256) k_roots(PlanTables t, const int32_t *__restrict__ J,
+                                               const double *__restrict__ misc, int32_t *__restrict__ r_o,
+                                               double *__restrict__ r_tau, double *__restrict__ r_a) {
     const int nj = t.status[1];
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nj) return;
+    const int lane = threadIdx.x & 63;
+    const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (r >= nj) return;   // the whole wave leaves
     const int n = t.n;
     const double rho = t.rho, znorm2 = misc[0];
     int pa, pb;
@@ -191,7 +197,7 @@ __global__ void k_roots(PlanTables t, const int32_t *__restrict__ J, const doubl
     double lo, hi;
     if (pa >= 0 && pb >= 0) {
         const double gap = lam_diff(t.sintab, n, pb, pa);
-        const Secular s = secular_eval(t, J, nj, pa, 0.5 * gap);
+        const Secular s = secular_eval_wave(t, J, nj, pa, 0.5 * gap, lane);
         const double za = t.z[pa];
         const double f = s.F - za * za / (0.5 * gap);
         if (f >= 0.0) {
@@ -207,10 +213,9 @@ __global__ void k_roots(PlanTables t, const int32_t *__restrict__ J, const doubl
     const double zo = t.z[o], zo2 = zo * zo;
     double tt = 0.5 * (lo + hi);
     Secular s{};
-    int it = 0;
     bool conv = false;
-    for (; it < 200; ++it) {
-        s = secular_eval(t, J, nj, o, tt);
+    for (int it = 0; it < 200; ++it) {
+        s = secular_eval_wave(t, J, nj, o, tt, lane);
         const double f = s.F - zo2 / tt;
         if (f > 0.0) hi = tt;
         else if (f < 0.0) lo = tt;
@@ -226,12 +231,14 @@ __global__ void k_roots(PlanTables t, const int32_t *__restrict__ J, const doubl
         }
         tt = tn;
     }
-    s = secular_eval(t, J, nj, o, tt);
+    s = secular_eval_wave(t, J, nj, o, tt, lane);
     const double fp = s.Fp + zo2 / (tt * tt);
-    r_o[r] = o;
-    r_tau[r] = tt;
-    r_a[r] = 1.0 / sqrt(fp);
-    if (!conv) t.status[0] |= 1;
+    if (lane == 0) {
+        r_o[r] = o;
+        r_tau[r] = tt;
+        r_a[r] = 1.0 / sqrt(fp);
+        if (!conv) atomicOr(&t.status[0], 1);
+    }
 }
 
 // Row ordering and per-row tables.  One workgroup.
@@ -381,7 +388,8 @@ __global__ void k_direct(PlanTables t) {
 }
 
 // Window transform 1 / phi_hat(l h), h = pi / 2n, by Gauss-Legendre quadrature
-// (nodes from Newton's method on the Legendre recurrence).
+// (nodes from Newton's method on the Legendre recurrence, recomputed by every
+// workgroup; each workgroup then covers its own range of frequencies l).
 __global__ void k_deconv(PlanTables t) {
     __shared__ double xq[kQuad], wq[kQuad];
     const int w = t.width;
@@ -407,7 +415,7 @@ __global__ void k_deconv(PlanTables t) {
     __syncthreads();
     const int n = t.n;
     const double h = M_PI / (2.0 * n);
-    for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < n; l += gridDim.x * blockDim.x) {
         double s = 0.0;
         for (int q = 0; q < kQuad; ++q) {
             const double u = 0.5 * w * xq[q];
@@ -474,13 +482,13 @@ dctplus_status plan_build(dctplus_plan_s *p, const double *v_host, hipStream_t s
                              ? sizeof(cplx<double>) * (n / 2)
                              : sizeof(int) * kPlanThreads;
     hipLaunchKernelGGL(k_z, dim3(1), dim3(kPlanThreads), lds_z, s, t, (const double *)v_dev, p->defl_tol, J, misc);
-    hipLaunchKernelGGL(k_roots, dim3((n + 127) / 128), dim3(128), 0, s, t, (const int32_t *)J,
-                       (const double *)misc, r_o, r_tau, r_a);
+    hipLaunchKernelGGL(k_roots, dim3((n + 3) / 4), dim3(256), 0, s, t, (const int32_t *)J, (const double *)misc,
+                       r_o, r_tau, r_a);
     const size_t lds_rows = sizeof(int) * (2 * n + 1);
     hipLaunchKernelGGL(k_rows, dim3(1), dim3(kPlanThreads), lds_rows, s, t, (const int32_t *)J,
                        (const double *)misc, (const int32_t *)r_o, (const double *)r_tau, (const double *)r_a,
                        p->direct_kappa, rowOfBin, rowOfK);
-    hipLaunchKernelGGL(k_deconv, dim3(1), dim3(256), 0, s, t);
+    hipLaunchKernelGGL(k_deconv, dim3((n + 255) / 256), dim3(256), 0, s, t);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "plan kernels");
 
     int32_t st[8];
