@@ -20,57 +20,79 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int GT = 64;      // output tile
-constexpr int GK = 16;      // batch rows per LDS stage
+constexpr int GT = 128;     // output tile (i and k)
+constexpr int GK = 32;      // batch rows per LDS stage
+constexpr int GP = GT + 4;  // LDS row stride (floats)
 
-// partial[split][i][k] = sum over this split's rows b of gy[b][i] * y[b][k]
+// partial[split][i][k] = sum over this split's rows b of gy[b][i] * y[b][k].
+// 128 x 128 tile per workgroup, 64 x 64 per wave (4 x 4 MFMA 16x16x4 tiles);
+// the next stage of rows is loaded into registers while the current one is
+// multiplied out of LDS.
 __global__ void __launch_bounds__(256) k_gram(const float *__restrict__ gy, const float *__restrict__ y,
                                               float *__restrict__ partial, int64_t batch, int n, int64_t rows_per) {
-    __shared__ float As[GK][GT + 1];   // gy tile [b][i]
-    __shared__ float Bs[GK][GT + 1];   // y tile  [b][k]
+    __shared__ float As[GK][GP];   // gy rows [b][i]
+    __shared__ float Bs[GK][GP];   // y rows  [b][k]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
     const int i0 = blockIdx.x * GT, k0 = blockIdx.y * GT, split = blockIdx.z;
     const int64_t b0 = (int64_t)split * rows_per;
     int64_t b1 = b0 + rows_per;
     if (b1 > batch) b1 = batch;
-    const int wi = (wave >> 1) * 32, wk = (wave & 1) * 32;
-    f4 acc[2][2];
+    const int wi = (wave >> 1) * 64, wk = (wave & 1) * 64;
+    f4 acc[4][4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    // stage loader: 32 rows x 128 columns of each operand, 16 floats per thread and operand
+    // thread t owns column c = t % 128 of rows t / 128 + 2u, u = 0 .. 15
+    float ra[16], rb[16];
+    const int c = tid & 127, r0 = tid >> 7;
+    const bool ci = i0 + c < n, ck = k0 + c < n;
+    const int64_t step = 2 * (int64_t)n;
+    auto fetch = [&](int64_t bb) {
+        const float *pa = gy + (bb + r0) * n + i0 + c;
+        const float *pb = y + (bb + r0) * n + k0 + c;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const bool rin = bb + r0 + 2 * u < b1;
+            ra[u] = (rin && ci) ? pa[u * step] : 0.0f;
+            rb[u] = (rin && ck) ? pb[u * step] : 0.0f;
+        }
+    };
+    fetch(b0);
     for (int64_t bb = b0; bb < b1; bb += GK) {
-        for (int e = tid; e < GK * GT; e += 256) {
-            const int r = e / GT, c = e % GT;
-            const int64_t row = bb + r;
-            As[r][c] = (row < b1 && i0 + c < n) ? gy[row * n + i0 + c] : 0.0f;
-            Bs[r][c] = (row < b1 && k0 + c < n) ? y[row * n + k0 + c] : 0.0f;
+        __syncthreads();                            // the previous stage is consumed
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            As[r0 + 2 * u][c] = ra[u];
+            Bs[r0 + 2 * u][c] = rb[u];
         }
         __syncthreads();
+        if (bb + GK < b1) fetch(bb + GK);           // in flight while this stage is multiplied
 #pragma unroll
         for (int s = 0; s < GK / 4; ++s) {
+            float av[4], bv[4];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                const float av = As[4 * s + lq][wi + 16 * a + l16];   // A[i][b] = gy[b][i]
+            for (int a = 0; a < 4; ++a) av[a] = As[4 * s + lq][wi + 16 * a + l16];   // A[i][b] = gy[b][i]
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const float bv = Bs[4 * s + lq][wk + 16 * b + l16];
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[a][b], 0, 0, 0);
-                }
-            }
+            for (int b = 0; b < 4; ++b) bv[b] = Bs[4 * s + lq][wk + 16 * b + l16];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
-        __syncthreads();
     }
-    float *P = partial + (size_t)split * n * n;
+    float *out = partial + (size_t)split * n * n;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int i = i0 + wi + 16 * a + 4 * lq + v, k = k0 + wk + 16 * b + l16;
-                if (i < n && k < n) P[(size_t)i * n + k] = acc[a][b][v];
+                if (i < n && k < n) out[(size_t)i * n + k] = acc[a][b][v];
             }
 }
 
@@ -195,7 +217,7 @@ dctplus_status grad_apply(dctplus_plan_s *p, const float *y, const float *gy, in
     const int tiles = nt * nt;
     int nsplit = 512 / tiles;
     if (nsplit < 1) nsplit = 1;
-    if (nsplit > 64) nsplit = 64;
+    if (nsplit > 128) nsplit = 128;
     while (nsplit > 1 && (size_t)nsplit * n * n * sizeof(float) > (size_t)256 << 20) nsplit >>= 1;
     int64_t rows_per = (batch + nsplit - 1) / nsplit;
     rows_per = (rows_per + GK - 1) / GK * GK;
