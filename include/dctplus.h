@@ -71,7 +71,7 @@ typedef enum {
 
 /* How the product with diag(a) C(mu, lambda) diag(z) is formed. */
 typedef enum {
-    DCTPLUS_ROUTE_AUTO = 0,  /* DENSE for n <= 4096, FAST above */
+    DCTPLUS_ROUTE_AUTO = 0,  /* DENSE (the FAST kernels are switched off in this build) */
     DCTPLUS_ROUTE_FAST = 1,  /* Alg. 1 / Thm 3.3: DCT-II, DST-I, sine NUFFT, O(n log n) */
     DCTPLUS_ROUTE_DENSE = 2, /* Thm 3.1: DCT-II, then an MFMA product with the n x n Cauchy factor */
     DCTPLUS_ROUTE_GFT = 3    /* dense GFT (the paper's naive product): MFMA product with X^T */
@@ -99,7 +99,8 @@ void dctplus_default_opts(dctplus_opts *opts);
  *   stream  : the plan's tables are computed on this stream (FP64 secular solve
  *             on the GPU); the call synchronises the stream once before returning.
  *   out     : receives the plan (owned by the caller, release with dctplus_plan_destroy).
- * The DENSE and GFT routes allocate an n x n matrix (4 n^2 bytes, plus 2 n^2 for BF16).
+ * The DENSE and GFT routes allocate an n x n matrix (4 n^2 bytes, plus 2 n^2 for BF16;
+ * 8 n^2 for FP64): 1 GiB in FP32 at n = 16384.
  */
 dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const dctplus_opts *opts,
                             void *stream, dctplus_plan_t *out);

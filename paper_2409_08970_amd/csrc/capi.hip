@@ -117,14 +117,13 @@ dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const d
     int route = o.route;
     if (route == DCTPLUS_ROUTE_AUTO) {
         // the FAST kernels are switched off in this build: every dtype takes the dense form
-        route = (n <= 4096) ? DCTPLUS_ROUTE_DENSE : DCTPLUS_ROUTE_FAST;
+        route = DCTPLUS_ROUTE_DENSE;
     }
     if ((o.dtype == DCTPLUS_BF16 || o.dtype == DCTPLUS_F32_SPLIT) && route == DCTPLUS_ROUTE_FAST)
         return fail(DCTPLUS_EUNSUPPORTED, "BF16 operands apply to the DENSE and GFT routes");
     if (o.dtype == DCTPLUS_F32_SPLIT && (n < 32 || n > 64))
         return fail(DCTPLUS_EUNSUPPORTED, "the split-BF16 mode supports n in {32, 64}");
-    if ((route == DCTPLUS_ROUTE_DENSE || route == DCTPLUS_ROUTE_GFT) && n > 4096)
-        return fail(DCTPLUS_EUNSUPPORTED, "dense routes support n <= 4096");
+
     if (o.dtype == DCTPLUS_BF16 && (n < 32 || n > 64))
         return fail(DCTPLUS_EUNSUPPORTED, "BF16 dense routes support n in {32, 64}");
 

@@ -39,54 +39,45 @@ __device__ __forceinline__ __bf16 bits2bf(uint16_t b) {
     return r;
 }
 
-// P rows in FP64 -> optional DCT-III along the row (GFT) -> FP32 / BF16.
-// One workgroup per row; LDS: n doubles + n/2 complex doubles.
+// P rows in FP64 -> optional DCT-III along the row (GFT) -> FP32 / BF16 / FP64.
+// One workgroup per row.  Row entries a z_j / (mu - lambda_j) (deflated rows:
+// e_o) are computed where they are needed; LDS holds only the n/2 complex
+// doubles of the FFT (gft) or the n doubles of the row (M itself).
 __global__ void __launch_bounds__(256) k_dense_rows(PlanTables t, int gft, float *__restrict__ P32,
                                                     uint16_t *__restrict__ P16, double *__restrict__ P64) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = t.n, logn = t.logn, i = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
-    double *row = reinterpret_cast<double *>(smem);
-    cplx<double> *Z = reinterpret_cast<cplx<double> *>(row + n);
     const int kind = t.kind[i];
     const int o = t.origin[i];
     const double tau = t.tau[i], a = t.a[i];
-    for (int j = tid; j < n; j += nthr) {
-        double v;
-        if (kind == ROW_DEFLATED) {
-            v = (j == o) ? 1.0 : 0.0;
-        } else {
-            const double zj = t.z[j];
-            const double sj = (j - o) >= 0 ? t.sintab[j - o] : -t.sintab[o - j];
-            const double d = 4.0 * sj * t.sintab[j + o];   // lambda_j - lambda_o
-            v = (zj != 0.0) ? a * zj / (tau - d) : 0.0;
-        }
-        row[j] = v;
-    }
-    __syncthreads();
+    auto entry = [&](int j) -> double {
+        if (kind == ROW_DEFLATED) return (j == o) ? 1.0 : 0.0;
+        const double zj = t.z[j];
+        if (zj == 0.0) return 0.0;
+        const double sj = (j - o) >= 0 ? t.sintab[j - o] : -t.sintab[o - j];
+        const double d = 4.0 * sj * t.sintab[j + o];   // lambda_j - lambda_o
+        return a * zj / (tau - d);
+    };
+    auto put = [&](int j, double v) {
+        if (P32) P32[(size_t)i * n + j] = (float)v;
+        if (P16) P16[(size_t)i * n + j] = f2bf((float)v);
+        if (P64) P64[(size_t)i * n + j] = v;
+    };
     if (gft) {
         // row i of X^T = (U m_i)^T: inverse orthonormal DCT of the row of M
+        cplx<double> *Z = reinterpret_cast<cplx<double> *>(smem);
         const int logT = logn + 2;
-        for (int k = tid; k < n / 2; k += nthr) {
-            auto get = [&](int kk) -> double { return row[kk]; };
-            Z[k] = dct3_pack<double>(get, k, logn, t.tw64, logT);
-        }
+        for (int k = tid; k < n / 2; k += nthr) Z[k] = dct3_pack<double>(entry, k, logn, t.tw64, logT);
         __syncthreads();
         const RadixPlan rp = radix_plan(logn - 1, 1, nthr);
         fft_dif(Z, 1, n / 2, logn - 1, t.tw64, logT, rp);
-        for (int j = tid; j < n; j += nthr) {
-            const double v = dct3_sample(Z, j, logn, rp);
-            if (P32) P32[(size_t)i * n + j] = (float)v;
-            if (P16) P16[(size_t)i * n + j] = f2bf((float)v);
-            if (P64) P64[(size_t)i * n + j] = v;
-        }
+        for (int j = tid; j < n; j += nthr) put(j, dct3_sample(Z, j, logn, rp));
     } else {
-        for (int j = tid; j < n; j += nthr) {
-            if (P32) P32[(size_t)i * n + j] = (float)row[j];
-            if (P16) P16[(size_t)i * n + j] = f2bf((float)row[j]);
-            if (P64) P64[(size_t)i * n + j] = row[j];
-        }
+        for (int j = tid; j < n; j += nthr) put(j, entry(j));
     }
 }
+
+size_t dense_rows_lds(int n, bool gft) { return gft ? sizeof(cplx<double>) * (n / 2) : 0; }
 
 // ---------------------------------------------------------------------------
 // Small n (16 <= N <= 64): persistent chunks of 64 signals.
@@ -760,7 +751,10 @@ dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s) {
             return fail(DCTPLUS_ENOMEM, "hipMalloc for the %d x %d FP64 dense factor failed", n, n);
         }
         p->t.folded = 1;
-        const size_t lds = sizeof(double) * n + sizeof(cplx<double>) * (n / 2);
+        const size_t lds = dense_rows_lds(n, true);
+        if (lds > 65536 && (e = hipFuncSetAttribute((const void *)k_dense_rows,
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
+            return hip_fail(e, "dense factor build (LDS size)");
         hipLaunchKernelGGL(k_dense_rows, dim3(n), dim3(256), lds, s, p->t, 1, (float *)nullptr,
                            (uint16_t *)nullptr, p->t.mt64);
         e = hipGetLastError();
@@ -792,7 +786,10 @@ dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s) {
     // factored progressive form is requested; both give the same transform.
     p->t.folded = (p->route == DCTPLUS_ROUTE_GFT) || !p->factored;
     const int gft = p->t.folded ? 1 : 0;
-    const size_t lds = sizeof(double) * n + sizeof(cplx<double>) * (n / 2);
+    const size_t lds = dense_rows_lds(n, gft != 0);
+    if (lds > 65536 && (e = hipFuncSetAttribute((const void *)k_dense_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                (int)lds)) != hipSuccess)
+        return hip_fail(e, "dense factor build (LDS size)");
     hipLaunchKernelGGL(k_dense_rows, dim3(n), dim3(256), lds, s, p->t, gft, p->t.mt32, p->t.mt16,
                        (double *)nullptr);
     e = hipGetLastError();

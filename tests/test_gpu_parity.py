@@ -143,17 +143,17 @@ def test_forward_and_adjoint_parity(route, n, kind):
     p.close()
 
 
-@FAST_SKIP
-@pytest.mark.parametrize("n", [4096, 16384])
+@pytest.mark.parametrize("route", [pytest.param("fast", marks=FAST_SKIP), "dense"])
+@pytest.mark.parametrize("n", [1024, 4096, 16384])
 @pytest.mark.parametrize("kind", ["dense", "edge"])
-def test_large_n_full_batch_sampled(n, kind):
+def test_large_n_full_batch_sampled(route, n, kind):
     """Workload-3 shape (256 N(0,1) signals): the whole batch runs on the GPU,
     sampled signals are checked against the semi-oracle, and the intertwining
     property X^T (L s) = mu * X^T s and Parseval are checked on every signal."""
     torch = _torch()
     W = workloads.workload3(n, kind)
     rho, v, x = W["rho"], W["v"], W["x"]
-    p = make_plan(n, rho, v, "fast")
+    p = make_plan(n, rho, v, route)
     y = run(p, x)
     rows = [0, 77, 255]
     sp = oracle.semi_plan(n, rho, v)
