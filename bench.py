@@ -278,25 +278,28 @@ def main():
                                args.steps, args.warmup)
         comp["dense_bf16_operands"] = {"ms_per_step": b_ms, "value": batch * n / (b_ms * 1e-3)}
         bp.close()
-        # large graph, n = 4096 (256 N(0,1) signals, dense unit v, rho = 0.5)
-        W3 = workloads.workload3(4096, "dense")
-        x3 = torch.from_numpy(W3["x"]).to(dev)
-        y3 = torch.empty_like(x3)
-        r3 = torch.empty_like(x3)
-        large = {}
-        for rt in ("dense", "gft"):
-            p3 = Plan(4096, W3["rho"], W3["v"], route=rt)
-            t3, _, _ = time_pair(torch, lambda: p3.forward(x3, out=y3), lambda: p3.adjoint(y3, out=r3),
+        # large graphs: 256 N(0,1) signals, dense unit v, rho = 0.5
+        for nl in (4096, 16384):
+            W3 = workloads.workload3(nl, "dense")
+            x3 = torch.from_numpy(W3["x"]).to(dev)
+            y3 = torch.empty_like(x3)
+            r3 = torch.empty_like(x3)
+            large = {}
+            for rt in ("dense", "gft"):
+                p3 = Plan(nl, W3["rho"], W3["v"], route=rt)
+                t3, _, _ = time_pair(torch, lambda: p3.forward(x3, out=y3), lambda: p3.adjoint(y3, out=r3),
+                                     max(3, args.steps // 4), 2)
+                large[rt] = {"ms_per_step": t3, "value": 256 * nl / (t3 * 1e-3)}
+                p3.close()
+            A = torch.randn(nl, nl, device=dev)
+            At = A.t().contiguous()
+            t3, _, _ = time_pair(torch, lambda: torch.matmul(x3, A, out=y3), lambda: torch.matmul(y3, At, out=r3),
                                  max(3, args.steps // 4), 2)
-            large[rt] = {"ms_per_step": t3, "value": 256 * 4096 / (t3 * 1e-3)}
-            p3.close()
-        A = torch.randn(4096, 4096, device=dev)
-        At = A.t().contiguous()
-        t3, _, _ = time_pair(torch, lambda: torch.matmul(x3, A, out=y3), lambda: torch.matmul(y3, At, out=r3),
-                             max(3, args.steps // 4), 2)
-        large["gft_torch_matmul"] = {"ms_per_step": t3, "value": 256 * 4096 / (t3 * 1e-3)}
-        large["fast"] = "FAST route switched off in this build"
-        comp["n4096_workload"] = large
+            large["gft_torch_matmul"] = {"ms_per_step": t3, "value": 256 * nl / (t3 * 1e-3)}
+            large["fast"] = "FAST route switched off in this build"
+            comp[f"n{nl}_workload"] = large
+            del A, At, x3, y3, r3
+            torch.cuda.empty_cache()
         result["comparators"] = comp
         for k, v in comp.items():
             print(k, v, file=sys.stderr, flush=True)
