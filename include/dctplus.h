@@ -85,6 +85,10 @@ typedef struct {
     double direct_kappa;  /* FAST route: rows whose NUFFT error amplification exceeds this are
                              summed exactly in FP64; <= 0 selects 1e5 */
     int32_t device;       /* HIP device ordinal; < 0 uses the current device */
+    int32_t factored;     /* DENSE route only, F32 or BF16: 1 keeps the two factors of Thm 3.1
+                             apart (a DCT-II of every signal, then the product with the Cauchy
+                             factor diag(a) C(mu, lambda) diag(z)); 0 (default) folds the DCT
+                             into one matrix X^T at plan time.  Same transform either way. */
 } dctplus_opts;
 
 /* Fill *opts with the defaults. */

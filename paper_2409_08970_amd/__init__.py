@@ -47,7 +47,7 @@ class Plan:
 
     def __init__(self, n: int, rho: float, v, route: str = "auto", dtype: str = "f32",
                  nufft_width: int = 0, direct_kappa: float = 0.0, defl_tol: float = 0.0, device: int = -1,
-                 stream=None):
+                 stream=None, factored: bool = False):
         import numpy as np
         import torch
         o = B.dctplus_default_opts()
@@ -62,6 +62,7 @@ class Plan:
         if device < 0:
             device = torch.cuda.current_device()
         o.device = device
+        o.factored = 1 if factored else 0
         self.n = int(n)
         self.rho = float(rho)
         self.v = np.asarray(v, dtype=np.float64).reshape(-1).copy()

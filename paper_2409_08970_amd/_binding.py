@@ -41,6 +41,7 @@ class dctplus_opts(ctypes.Structure):
         ("nufft_width", ctypes.c_int32),
         ("direct_kappa", ctypes.c_double),
         ("device", ctypes.c_int32),
+        ("factored", ctypes.c_int32),
     ]
 
 

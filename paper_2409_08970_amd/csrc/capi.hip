@@ -89,6 +89,7 @@ void dctplus_default_opts(dctplus_opts *o) {
     o->nufft_width = 12;
     o->direct_kappa = 1e5;
     o->device = -1;
+    o->factored = 0;
 }
 
 dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const dctplus_opts *opts, void *stream,
@@ -126,6 +127,9 @@ dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const d
 
     if (o.dtype == DCTPLUS_BF16 && (n < 32 || n > 64))
         return fail(DCTPLUS_EUNSUPPORTED, "BF16 dense routes support n in {32, 64}");
+    if (o.factored != 0 && o.factored != 1) return fail(DCTPLUS_EINVAL, "factored must be 0 or 1");
+    if (o.factored && (route != DCTPLUS_ROUTE_DENSE || (o.dtype != DCTPLUS_F32 && o.dtype != DCTPLUS_BF16)))
+        return fail(DCTPLUS_EUNSUPPORTED, "the factored form is available on the DENSE route for F32 and BF16");
 
     int dev = o.device;
     hipError_t e;
@@ -146,6 +150,7 @@ dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const d
     p->defl_tol = o.defl_tol;
     p->direct_kappa = o.direct_kappa;
     p->width = o.nufft_width;
+    p->factored = o.factored;
     dctplus_status st = plan_build(p, v_host, (hipStream_t)stream);
     if (st != DCTPLUS_OK) {
         dctplus_plan_destroy(p);

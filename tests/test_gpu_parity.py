@@ -95,8 +95,12 @@ def run(plan, arr, adjoint=False):
 
 
 def make_plan(n, rho, v, route, dtype="f32", **kw):
+    """route "dense-factored": the DENSE route with the two factors of Thm 3.1 kept
+    apart (DCT-II on the GPU, then the Cauchy factor)."""
     _torch()
     from paper_2409_08970_amd import Plan
+    if route == "dense-factored":
+        return Plan(n, rho, v, route="dense", dtype=dtype, factored=True, **kw)
     return Plan(n, rho, v, route=route, dtype=dtype, **kw)
 
 
@@ -123,7 +127,8 @@ def test_plan_spectrum_matches_oracle(n, kind):
 
 ROUTE_SIZES = [pytest.param("fast", n, marks=FAST_SKIP) for n in (4, 8, 16, 32, 64, 128, 256, 1024)] + \
               [("dense", n) for n in (4, 8, 16, 32, 64, 128, 256)] + \
-              [("gft", n) for n in (4, 8, 16, 32, 64, 128, 256)]
+              [("gft", n) for n in (4, 8, 16, 32, 64, 128, 256)] + \
+              [("dense-factored", n) for n in (4, 8, 16, 32, 64, 128, 256, 1024)]
 
 
 @pytest.mark.parametrize("route,n", ROUTE_SIZES)
@@ -254,7 +259,7 @@ def test_fp64_dense_parity(route, n, kind):
         assert relerr(xa, oracle.adjoint(X, yin)) <= tol, (route, n, kind, tol)
 
 
-@pytest.mark.parametrize("route", ["dense", "gft"])
+@pytest.mark.parametrize("route", ["dense", "gft", "dense-factored"])
 @pytest.mark.parametrize("n", [32, 64])
 def test_bf16_operands(route, n):
     rho, v = case(n, "dense")
