@@ -16,8 +16,9 @@
 // dctplus_select is one persistent launch.  Workgroups take blocks from an
 // atomic work queue (largest n_b first).  Per block: the S signals go to LDS;
 // each signal's path-Laplacian quadratic form decides whether it is pruned
-// (x^T L_path x <= tau ||x||^2); one DCT-II of all signals runs in LDS and is
-// shared by every candidate (the progressive property); each candidate's
+// (x^T L_path x <= tau ||x||^2); one DCT-II of all signals (a product with the
+// DCT matrix on MFMA, in LDS) is shared by every candidate (the progressive
+// property); each candidate's
 // coefficients C~_r s_d follow on MFMA (pruned signals keep the upper-left
 // c_p x c_p block of C~_r, Thm 3.4); the L1 norm of the coefficients is the
 // candidate's cost; the lowest cost wins (ties: lowest index) and the
@@ -45,7 +46,7 @@ struct dctplus_select_s {
     int32_t *counter_dev = nullptr;   // work-queue head
     int32_t *status_dev = nullptr;
     float *M = nullptr;               // all factors
-    dctplus::cplx<float> *tw = nullptr;   // DFT twiddles for the five sizes
+    float *dctm = nullptr;            // orthonormal DCT-II matrices of the five sizes (factor layout)
 };
 
 namespace dctplus {
@@ -67,8 +68,9 @@ __host__ __device__ __forceinline__ int64_t sel_frag_index(int n, int i, int k) 
     return ((int64_t)((c * (n >> 4) + (s >> 2)) * 64 + lane) << 2) + (s & 3);
 }
 
-// start of the 4n-entry twiddle table of size n (tables for n = 4, 8, ..., 64 back to back)
-__host__ __device__ __forceinline__ int sel_tw_offset(int n) { return 4 * (n - 4); }
+// start of the n x n DCT matrix of size n (matrices for n = 4, 8, ..., 64 back to back:
+// 16 + 64 + ... + (n/2)^2 = (n^2 - 16) / 3 floats before it)
+__host__ __device__ __forceinline__ int sel_dct_offset(int n) { return (n * n - 16) / 3; }
 
 // ---------------------------------------------------------------------------
 // Batched FP64 candidate plans: one 64-thread workgroup per candidate.
@@ -218,14 +220,15 @@ __global__ void __launch_bounds__(64) k_select_plan(const int32_t *__restrict__ 
     }
 }
 
-// twiddles exp(-2 pi i k / 4n) for n = 4, 8, 16, 32, 64, one table after the other
-__global__ void k_select_twiddles(cplx<float> *tw) {
+// DCT-II matrices A[i][j] = c_i cos(pi i (2j + 1) / 2n) (row i = frequency i, so that
+// s_d = A x) for n = 4, 8, 16, 32, 64, stored like the candidate factors.
+__global__ void k_select_dctm(float *dctm) {
     for (int n = 4; n <= kSelMaxN; n *= 2) {
-        const int T = 4 * n;
-        for (int k = threadIdx.x; k < T; k += blockDim.x) {
-            double s, c;
-            sincospi(2.0 * k / T, &s, &c);
-            tw[sel_tw_offset(n) + k] = {(float)c, (float)-s};
+        float *D = dctm + sel_dct_offset(n);
+        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += gridDim.x * blockDim.x) {
+            const int i = e / n, j = e % n;
+            const double ci = (i == 0) ? sqrt(1.0 / n) : sqrt(2.0 / n);
+            D[sel_frag_index(n, i, j)] = (float)(ci * cospi((double)i * (2 * j + 1) / (2.0 * n)));
         }
     }
 }
@@ -246,7 +249,7 @@ struct SelArgs {
     const int32_t *order;
     int32_t *counter;
     const float *M;
-    const cplx<float> *tw;
+    const float *dctm;
     int64_t nblocks;
     int K, S, cp;
     double tau;
@@ -257,37 +260,64 @@ struct SelArgs {
 
 struct SelShared {
     float xs[kSelMaxS * (kSelMaxN + 1)];     // signals, then their DCT-II (row stride n + 1)
-    cplx<float> Z[kSelMaxS * (kSelMaxN / 2)];
     float cost[kSelMaxK];
     int pruned[kSelMaxS];
     int next;
     int best;
 };
 
+// DCT-II of the block's 64 rows of xs, in place, as one product with the DCT
+// matrix.  n >= 16: wave w transforms the 16 signals of tile w on 16x16x4 FP32
+// MFMA (each lane reads its samples before any lane of the wave writes, and the
+// wave touches only its own rows).  n < 16: thread s < 64 transforms signal s.
 template <int N>
-constexpr int ilog2() { return N <= 1 ? 0 : 1 + ilog2<N / 2>(); }
-
-// DCT-II of the 64 rows of xs, in place (Makhoul packing, N/2-point complex FFT).
-template <int N>
-__device__ __forceinline__ void sel_dct(SelShared &sh, const cplx<float> *__restrict__ tw) {
-    constexpr int Mh = N / 2, logN = ilog2<N>(), logT = logN + 2;
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    const RadixPlan rp = radix_plan(logN - 1, kSelMaxS, nthr);
-    __syncthreads();
-    for (int g = tid; g < kSelMaxS * Mh; g += nthr) {
-        const int s = g / Mh, m = g % Mh;
-        sh.Z[s * Mh + m] = dct2_pack<float>(sh.xs + s * (N + 1), m, N);
+__device__ __forceinline__ void sel_dct(SelShared &sh, const float *__restrict__ D) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if constexpr (N >= 16) {
+        constexpr int CT = N / 16, KS = N / 4;
+        const int l16 = lane & 15, g = lane >> 4;
+        const float4 *D4 = reinterpret_cast<const float4 *>(D);
+        float *row = sh.xs + (16 * wave + l16) * (N + 1);
+        f4 acc[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[c] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s4 = 0; s4 < KS / 4; ++s4) {
+            float4 q[CT];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) q[c] = D4[(c * (KS / 4) + s4) * 64 + lane];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float bv = row[4 * (4 * s4 + e) + g];
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    const float a = e == 0 ? q[c].x : e == 1 ? q[c].y : e == 2 ? q[c].z : q[c].w;
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[c], 0, 0, 0);
+                }
+            }
+        }
+        // lane holds coefficients i = 16 c + 4 g + v of its signal
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) row[16 * c + 4 * g + v] = acc[c][v];
+    } else {
+        if (threadIdx.x < 64) {
+            float *row = sh.xs + threadIdx.x * (N + 1);
+            float xv[N], sd[N];
+#pragma unroll
+            for (int j = 0; j < N; ++j) xv[j] = row[j];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                float acc = 0.f;
+#pragma unroll
+                for (int j = 0; j < N; ++j) acc += D[i * N + j] * xv[j];
+                sd[i] = acc;
+            }
+#pragma unroll
+            for (int i = 0; i < N; ++i) row[i] = sd[i];
+        }
     }
-    __syncthreads();
-    fft_dif(sh.Z, kSelMaxS, Mh, logN - 1, tw, logT, rp);
-    for (int g = tid; g < kSelMaxS * (Mh + 1); g += nthr) {
-        const int s = g / (Mh + 1), k = g % (Mh + 1);
-        float Xk, XNk;
-        dct2_post(sh.Z + s * Mh, k, logN, rp, tw, logT, Xk, XNk);
-        sh.xs[s * (N + 1) + k] = Xk;
-        if (k > 0 && k < Mh) sh.xs[s * (N + 1) + N - k] = XNk;
-    }
-    __syncthreads();
 }
 
 // y_sig = C~_r s_d(sig) on 16x16x4 FP32 MFMA (n >= 16) for the signal tiles
@@ -343,6 +373,62 @@ __device__ __forceinline__ float sel_product_mfma(const SelShared &sh, const flo
     return l1;
 }
 
+// One candidate's coefficients y_sig = C~_r s_d(sig) on 16x16x4 FP32 MFMA (n >= 16):
+// wave w computes output rows 16 c .. 16 c + 15, c = w mod (n/16), for n/16 of the
+// four signal tiles, so the four waves together read the factor once and hold
+// only n/16 accumulators each.  Pruned signals keep the c_p x c_p block.  Returns
+// this lane's share of sum |y|; writes y when yout != nullptr.
+template <int N>
+__device__ __forceinline__ float sel_tiles(const SelShared &sh, const float *__restrict__ Mr, int cp, int ntile,
+                                           int S, float *__restrict__ yout) {
+    constexpr int CT = N / 16, KS = N / 4, G = 4 / CT;   // G waves share an output tile
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
+    const int c = wave % CT, grp = wave / CT;
+    const float4 *M4 = reinterpret_cast<const float4 *>(Mr);
+    bool pr[CT];
+    f4 acc[CT];
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+        pr[j] = sh.pruned[16 * (grp + j * G) + l16] != 0;
+        acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < KS / 4; ++s4) {
+        const float4 q = M4[(c * (KS / 4) + s4) * 64 + lane];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = 4 * (4 * s4 + e) + g;
+            const float a = e == 0 ? q.x : e == 1 ? q.y : e == 2 ? q.z : q.w;
+#pragma unroll
+            for (int j = 0; j < CT; ++j) {
+                // rows past the block's signals are zero: no test needed here
+                const int t = grp + j * G;
+                float bv = sh.xs[(16 * t + l16) * (N + 1) + k];
+                if (pr[j] && k >= cp) bv = 0.f;
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[j], 0, 0, 0);
+            }
+        }
+    }
+    float l1 = 0.f;
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+        const int t = grp + j * G;
+        if (t >= ntile) continue;
+        const int sig = 16 * t + l16;
+        float v4[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 16 * c + 4 * g + v;
+            v4[v] = (pr[j] && i >= cp) ? 0.f : acc[j][v];
+            l1 += fabsf(v4[v]);
+        }
+        if (yout && sig < S)
+            *reinterpret_cast<float4 *>(yout + (int64_t)sig * N + 16 * c + 4 * g) =
+                make_float4(v4[0], v4[1], v4[2], v4[3]);
+    }
+    return l1;
+}
+
 // The same for n in {4, 8} on the vector ALU: one signal per lane.
 template <int N>
 __device__ __forceinline__ float sel_product_valu(const SelShared &sh, const float *__restrict__ Mr, int cp, int S,
@@ -388,7 +474,9 @@ __device__ __forceinline__ void sel_block(SelShared &sh, const SelArgs &A, int64
         }
         sh.pruned[tid] = (q <= A.tau * e2) ? 1 : 0;
     }
-    sel_dct<N>(sh, A.tw + sel_tw_offset(N));   // begins and ends with a barrier
+    __syncthreads();                            // the pruning test has read the raw rows
+    sel_dct<N>(sh, A.dctm + sel_dct_offset(N));
+    __syncthreads();
     const int cp = (A.cp <= 0) ? (N / 2 > 2 ? N / 2 : 2) : (A.cp < N ? A.cp : N);
     const int ntile = (S + 15) / 16;
     const float *Mb = A.M + A.moff[b];
@@ -412,7 +500,7 @@ __device__ __forceinline__ void sel_block(SelShared &sh, const SelArgs &A, int64
     // the winner's coefficients, recomputed (one signal tile per wave)
     float *yb = A.y + A.xoff[b];
     const float *Mw = Mb + (int64_t)sh.best * N * N;
-    if constexpr (N >= 16) (void)sel_product_mfma<N>(sh, Mw, cp, wave, nwave, ntile, S, yb);
+    if constexpr (N >= 16) (void)sel_tiles<N>(sh, Mw, cp, ntile, S, yb);
     else if (wave == 0) (void)sel_product_valu<N>(sh, Mw, cp, S, yb);
     __syncthreads();
 }
@@ -517,7 +605,7 @@ dctplus_status dctplus_select_plan(int64_t nblocks, int32_t K, int32_t S, const 
         hipMalloc(&p->moff_dev, sizeof(int64_t) * nblocks) != hipSuccess ||
         hipMalloc(&p->order_dev, sizeof(int32_t) * nblocks) != hipSuccess ||
         hipMalloc(&p->counter_dev, 256) != hipSuccess || hipMalloc(&p->status_dev, 256) != hipSuccess ||
-        hipMalloc(&p->tw, sizeof(cplx<float>) * sel_tw_offset(2 * kSelMaxN)) != hipSuccess ||
+        hipMalloc(&p->dctm, sizeof(float) * sel_dct_offset(2 * kSelMaxN)) != hipSuccess ||
         hipMalloc(&p->M, sizeof(float) * (size_t)ma) != hipSuccess ||
         hipMalloc(&cand_dev, sizeof(double) * 4 * (size_t)nblocks * K) != hipSuccess) {
         (void)hipGetLastError();
@@ -536,7 +624,7 @@ dctplus_status dctplus_select_plan(int64_t nblocks, int32_t K, int32_t S, const 
                             s)) != hipSuccess ||
         (e = hipMemsetAsync(p->status_dev, 0, sizeof(int32_t), s)) != hipSuccess)
         return bail(hip_fail(e, "selection plan upload"));
-    hipLaunchKernelGGL(k_select_twiddles, dim3(1), dim3(256), 0, s, p->tw);
+    hipLaunchKernelGGL(k_select_dctm, dim3(16), dim3(256), 0, s, p->dctm);
     hipLaunchKernelGGL(k_select_plan, dim3((unsigned)(nblocks * K)), dim3(64), 0, s, (const int32_t *)p->n_dev,
                        (const double *)cand_dev, (const int64_t *)p->moff_dev, (int)K, p->M, p->status_dev);
     if ((e = hipGetLastError()) != hipSuccess) return bail(hip_fail(e, "selection plan launch"));
@@ -578,7 +666,7 @@ dctplus_status dctplus_select(dctplus_select_t p, const float *x, int32_t c_p, d
     A.order = p->order_dev;
     A.counter = p->counter_dev;
     A.M = p->M;
-    A.tw = p->tw;
+    A.dctm = p->dctm;
     A.nblocks = p->nblocks;
     A.K = p->K;
     A.S = p->S;
@@ -623,7 +711,7 @@ void dctplus_select_destroy(dctplus_select_t p) {
     if (p->order_dev) (void)hipFree(p->order_dev);
     if (p->counter_dev) (void)hipFree(p->counter_dev);
     if (p->status_dev) (void)hipFree(p->status_dev);
-    if (p->tw) (void)hipFree(p->tw);
+    if (p->dctm) (void)hipFree(p->dctm);
     if (p->M) (void)hipFree(p->M);
     delete p;
 }
