@@ -320,12 +320,13 @@ __device__ __forceinline__ void sel_dct(SelShared &sh, const float *__restrict__
     }
 }
 
-// y_sig = C~_r s_d(sig) on 16x16x4 FP32 MFMA (n >= 16) for the signal tiles
-// t0, t0 + tstep, ... < ntile; pruned signals are masked to the c_p x c_p block.
-// Returns this lane's share of sum |y|; writes y when yout != nullptr.
+// Cost of one candidate (n >= 16): sum over the block's 64 signal rows of
+// |C~_r s_d| on 16x16x4 FP32 MFMA, one wave, the factor held in registers and
+// reused for the four signal tiles (rows past the block's signals are zero, so
+// all four tiles run unconditionally).  Pruned signals keep the c_p x c_p block.
+// Returns this lane's share.
 template <int N>
-__device__ __forceinline__ float sel_product_mfma(const SelShared &sh, const float *__restrict__ Mr, int cp,
-                                                  int t0, int tstep, int ntile, int S, float *__restrict__ yout) {
+__device__ __forceinline__ float sel_cost_mfma(const SelShared &sh, const float *__restrict__ Mr, int cp) {
     constexpr int CT = N / 16, KS = N / 4;
     const int lane = threadIdx.x & 63, l16 = lane & 15, g = lane >> 4;
     const float4 *M4 = reinterpret_cast<const float4 *>(Mr);
@@ -341,7 +342,8 @@ __device__ __forceinline__ float sel_product_mfma(const SelShared &sh, const flo
             a[c][4 * s4 + 3] = q.w;
         }
     float l1 = 0.f;
-    for (int tile = t0; tile < ntile; tile += tstep) {
+#pragma unroll 1
+    for (int tile = 0; tile < kSelMaxS / 16; ++tile) {
         const int sig = 16 * tile + l16;
         const bool pr = sh.pruned[sig] != 0;
         f4 acc[CT];
@@ -357,18 +359,12 @@ __device__ __forceinline__ float sel_product_mfma(const SelShared &sh, const flo
         }
         // this lane holds outputs i = 16 c + 4 g + v of signal sig
 #pragma unroll
-        for (int c = 0; c < CT; ++c) {
-            float v4[4];
+        for (int c = 0; c < CT; ++c)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int i = 16 * c + 4 * g + v;
-                v4[v] = (pr && i >= cp) ? 0.f : acc[c][v];
-                l1 += fabsf(v4[v]);
+                l1 += (pr && i >= cp) ? 0.f : fabsf(acc[c][v]);
             }
-            if (yout && sig < S)
-                *reinterpret_cast<float4 *>(yout + (int64_t)sig * N + 16 * c + 4 * g) =
-                    make_float4(v4[0], v4[1], v4[2], v4[3]);
-        }
     }
     return l1;
 }
@@ -482,7 +478,7 @@ __device__ __forceinline__ void sel_block(SelShared &sh, const SelArgs &A, int64
     const float *Mb = A.M + A.moff[b];
     for (int r = wave; r < K; r += nwave) {
         float l1;
-        if constexpr (N >= 16) l1 = sel_product_mfma<N>(sh, Mb + (int64_t)r * N * N, cp, 0, 1, ntile, S, nullptr);
+        if constexpr (N >= 16) l1 = sel_cost_mfma<N>(sh, Mb + (int64_t)r * N * N, cp);
         else l1 = sel_product_valu<N>(sh, Mb + (int64_t)r * N * N, cp, S, nullptr);
         l1 = wave_sum(l1);
         if (lane == 0) sh.cost[r] = l1;
