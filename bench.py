@@ -278,6 +278,21 @@ def main():
                                args.steps, args.warmup)
         comp["dense_bf16_operands"] = {"ms_per_step": b_ms, "value": batch * n / (b_ms * 1e-3)}
         bp.close()
+        # the same workload at n = 32 (2^20 AR(0.95) signals), both FP32-accurate configurations
+        W32 = workloads.workload2(32)
+        x32 = torch.from_numpy(W32["x"]).to(dev)
+        y32 = torch.empty_like(x32)
+        r32 = torch.empty_like(x32)
+        n32 = {}
+        for dt in ("f32", "f32split"):
+            p32 = Plan(32, W32["rho"], W32["v"], route="auto", dtype=dt)
+            t32, _, _ = time_pair(torch, lambda: p32.forward(x32, out=y32), lambda: p32.adjoint(y32, out=r32),
+                                  args.steps, args.warmup)
+            n32[dt] = {"ms_per_step": t32, "value": x32.shape[0] * 32 / (t32 * 1e-3),
+                       "hbm_gbs": 2 * 2 * x32.numel() * 4 / (t32 * 1e-3) / 1e9}
+            p32.close()
+        comp["n32_workload"] = n32
+        del x32, y32, r32
         # large graphs: 256 N(0,1) signals, dense unit v, rho = 0.5
         for nl in (4096, 16384):
             W3 = workloads.workload3(nl, "dense")
