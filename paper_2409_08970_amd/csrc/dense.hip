@@ -285,8 +285,16 @@ __global__ void __launch_bounds__(256, 4) k_dense_stream(const float *__restrict
     constexpr int KQ = C::KQ, CT = C::CT, V4 = C::V4, D = C::kDepth;
     constexpr int NS = CT * (KQ / 8);                // BF16 fragments per piece
     __shared__ __align__(16) unsigned char sa[stream_lds_bytes<N, MODE>()];
+    // per-wave staging of one tile (16 rows of N/4 float4 chunks): tiles move between
+    // HBM and registers as contiguous 1 KiB pieces and are re-laid out here
+    constexpr int CH = N / 4;                        // float4 chunks per row
+    __shared__ f4 stage[4][16 * CH];
     const int tid = threadIdx.x, lane = tid & 63;
     const int l16 = lane & 15, g = lane >> 4;
+    f4 *st = stage[tid >> 6];
+    // chunk `ch` of row `r` sits at r * CH + (ch ^ (r mod CH)): conflict-free both for a
+    // row-contiguous sweep and for sixteen rows read at one chunk position
+    auto spos = [](int r, int ch) -> int { return r * CH + (ch ^ (r & (CH - 1))); };
     // Full tiles (16 valid signals) run branch-free: prefetch addresses are
     // clamped to the last full tile, so every load is issued unconditionally and
     // the wait counts stay exact (a guarded load makes the compiler wait for all
@@ -294,13 +302,24 @@ __global__ void __launch_bounds__(256, 4) k_dense_stream(const float *__restrict
     const int64_t nfull = batch / 16;
     const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    // float4 number v of a lane is chunk 4 v + g of its signal's row, so the four
-    // lanes of a signal read 64 contiguous bytes per load instruction
+    // a full tile is 16 N contiguous floats: lane l reads chunks 64 u + l (coalesced)
     auto loadc = [&](int64_t tile, f4 *b) {
         const int64_t t = tile < nfull ? tile : nfull - 1;
-        const f4 *src = reinterpret_cast<const f4 *>(in + (t * 16 + l16) * N);
+        const f4 *src = reinterpret_cast<const f4 *>(in + t * 16 * N);
 #pragma unroll
-        for (int v = 0; v < V4; ++v) b[v] = src[4 * v + g];
+        for (int u = 0; u < V4; ++u) b[u] = src[64 * u + lane];
+    };
+    // coalesced chunks -> staging -> this lane's operand chunks 4 v + g of row l16
+    auto relayout_in = [&](f4 *b) {
+#pragma unroll
+        for (int u = 0; u < V4; ++u) {
+            const int L = 64 * u + lane;
+            st[spos(L / CH, L % CH)] = b[u];
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int v = 0; v < V4; ++v) b[v] = st[spos(l16, 4 * v + g)];
+        __builtin_amdgcn_wave_barrier();
     };
     // the first kDepth tiles are requested before the A operands are built
     f4 ring[D][V4];
@@ -396,11 +415,26 @@ __global__ void __launch_bounds__(256, 4) k_dense_stream(const float *__restrict
                 }
             }
         }
-        const int64_t sig = tile * 16 + l16;
-        if (!guarded || sig < batch) {
-            f4 *dst = reinterpret_cast<f4 *>(out + sig * N + 4 * g);
+        if (guarded) {
+            const int64_t sig = tile * 16 + l16;
+            if (sig < batch) {
+                f4 *dst = reinterpret_cast<f4 *>(out + sig * N + 4 * g);
 #pragma unroll
-            for (int c = 0; c < CT; ++c) dst[4 * c] = acc[c];
+                for (int c = 0; c < CT; ++c) dst[4 * c] = acc[c];
+            }
+        } else {
+            // outputs 16 c + 4 g .. + 3 of row l16 are chunk 4 c + g: stage, then store
+            // the tile as contiguous 1 KiB pieces
+#pragma unroll
+            for (int c = 0; c < CT; ++c) st[spos(l16, 4 * c + g)] = acc[c];
+            __builtin_amdgcn_wave_barrier();
+            f4 *dst = reinterpret_cast<f4 *>(out + tile * 16 * N);
+#pragma unroll
+            for (int u = 0; u < V4; ++u) {
+                const int L = 64 * u + lane;
+                dst[L] = st[spos(L / CH, L % CH)];
+            }
+            __builtin_amdgcn_wave_barrier();
         }
     };
     if (nfull > 0) {
@@ -408,13 +442,17 @@ __global__ void __launch_bounds__(256, 4) k_dense_stream(const float *__restrict
         for (; base + (D - 1) * nwaves < nfull; base += D * nwaves) {
 #pragma unroll
             for (int d = 0; d < D; ++d) {
+                relayout_in(ring[d]);
                 compute_store(base + d * nwaves, ring[d], false);
                 loadc(base + (d + D) * nwaves, ring[d]);
             }
         }
 #pragma unroll
         for (int d = 0; d < D - 1; ++d)
-            if (base + d * nwaves < nfull) compute_store(base + d * nwaves, ring[d], false);
+            if (base + d * nwaves < nfull) {
+                relayout_in(ring[d]);
+                compute_store(base + d * nwaves, ring[d], false);
+            }
     }
     if (nfull * 16 < batch && wave0 == nfull % nwaves) {
         // the ragged last tile: guarded loads (zeros past the batch) and stores
