@@ -254,7 +254,7 @@ void dctplus_plan_destroy(dctplus_plan_t p) {
     if (p->t.mt32) (void)hipFree(p->t.mt32);
     if (p->t.mt16) (void)hipFree(p->t.mt16);
     if (p->t.mt64) (void)hipFree(p->t.mt64);
-    if (p->blas) dense_release(p);
+    dense_release(p);
     if (p->work) (void)hipFree(p->work);
     if (p->dev_mem) (void)hipFree(p->dev_mem);
     if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);

@@ -71,6 +71,8 @@ struct dctplus_plan_s {
     void *work;               // lazily grown workspace (FFT scratch for large n, gradient)
     size_t work_bytes;
     void *blas;               // hipBLASLt set-up of the FP32 dense product for n > 64 (plain GEMM)
+    void *simg;               // LDS images of the streaming kernel's operands (forward, adjoint), n <= 64
+    size_t simg_bytes;        // bytes of one image
     dctplus::PlanTables t;
 };
 

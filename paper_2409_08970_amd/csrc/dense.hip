@@ -274,13 +274,55 @@ constexpr int stream_lds_bytes() {
                      : (MODE == 1 ? 1 : 3) * StreamCfg<N>::CT * (StreamCfg<N>::KQ / 8) * 64 * 16;
 }
 
+// The LDS image of the streaming kernel's A operands (A = P forward, P^T adjoint), built
+// once per plan and direction and copied into LDS by every workgroup.  Lane (l16, g)
+// holds sample sigma(q, g) = 16 (q / 4) + 4 g + q % 4 of its signal as its q-th B value.
+//   MODE 0: float  [CT][KQ/4][64 lanes][4]
+//   MODE 1: bf16   [NS][64 lanes][8]
+//   MODE 2: bf16   [3 pieces][NS][64 lanes][8]   (h, m, l of the three-piece split)
+template <int N, int MODE>
+__global__ void __launch_bounds__(256) k_stream_image(const float *__restrict__ P32, const uint16_t *__restrict__ P16,
+                                                     int adj, unsigned char *__restrict__ img) {
+    using C = StreamCfg<N>;
+    constexpr int KQ = C::KQ, CT = C::CT;
+    constexpr int NS = CT * (KQ / 8);
+    auto sigma = [](int q, int gg) -> int { return 16 * (q >> 2) + 4 * gg + (q & 3); };
+    auto aval = [&](int row, int col) -> float {
+        return adj ? P32[(size_t)col * N + row] : P32[(size_t)row * N + col];
+    };
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x, nthr = gridDim.x * blockDim.x;
+    if constexpr (MODE == 0) {
+        float *af = reinterpret_cast<float *>(img);
+        for (int e = tid; e < CT * KQ * 64; e += nthr) {
+            const int q4 = e & 3, ln = (e >> 2) & 63, rest = e >> 8;   // rest = c * (KQ/4) + qq
+            const int c = rest / (KQ / 4), qq = rest % (KQ / 4);
+            af[e] = aval(16 * c + (ln & 15), sigma(4 * qq + q4, ln >> 4));
+        }
+    } else {
+        uint16_t *af = reinterpret_cast<uint16_t *>(img);
+        for (int e = tid; e < NS * 64 * 8; e += nthr) {
+            const int el = e & 7, ln = (e >> 3) & 63, f = e >> 9;      // f = c * (KQ/8) + st
+            const int c = f / (KQ / 8), st = f % (KQ / 8);
+            const int row = 16 * c + (ln & 15), col = sigma(8 * st + el, ln >> 4);
+            if constexpr (MODE == 1) {
+                af[e] = adj ? P16[(size_t)col * N + row] : P16[(size_t)row * N + col];
+            } else {
+                uint16_t h, m, l;
+                split3(aval(row, col), h, m, l);
+                af[e] = h;
+                af[NS * 512 + e] = m;
+                af[2 * NS * 512 + e] = l;
+            }
+        }
+    }
+}
+
 // MODE 0: FP32 MFMA.  MODE 1: BF16 operands.  MODE 2: FP32-accurate products from
 // three-piece BF16 splits of both operands, keeping the six cross products of
 // order >= 2^-16 (hh, hm, mh, mm, hl, lh) with FP32 accumulation.
 template <int N, int MODE>
 __global__ void __launch_bounds__(256, 4) k_dense_stream(const float *__restrict__ in, float *__restrict__ out,
-                                                      int64_t batch, const float *__restrict__ P32,
-                                                      const uint16_t *__restrict__ P16, int adj) {
+                                                      int64_t batch, const unsigned char *__restrict__ img) {
     using C = StreamCfg<N>;
     constexpr int KQ = C::KQ, CT = C::CT, V4 = C::V4, D = C::kDepth;
     constexpr int NS = CT * (KQ / 8);                // BF16 fragments per piece
@@ -327,36 +369,11 @@ __global__ void __launch_bounds__(256, 4) k_dense_stream(const float *__restrict
 #pragma unroll
         for (int d = 0; d < D; ++d) loadc(wave0 + d * nwaves, ring[d]);
     }
-    // A operands into LDS in lane order.  Lane (l16, g) holds sample
-    // sigma(q, g) = 16 (q / 4) + 4 g + q % 4 of its signal as its q-th B value.
-    auto sigma = [](int q, int gg) -> int { return 16 * (q >> 2) + 4 * gg + (q & 3); };
-    auto aval = [&](int row, int col) -> float {
-        return adj ? P32[(size_t)col * N + row] : P32[(size_t)row * N + col];
-    };
-    if constexpr (MODE == 0) {
-        float *af = reinterpret_cast<float *>(sa);    // [CT][KQ/4][64 lanes][4]
-        for (int e = tid; e < CT * KQ * 64; e += blockDim.x) {
-            const int q4 = e & 3, ln = (e >> 2) & 63, rest = e >> 8;   // rest = c * (KQ/4) + qq
-            const int c = rest / (KQ / 4), qq = rest % (KQ / 4);
-            const int q = 4 * qq + q4;
-            af[e] = aval(16 * c + (ln & 15), sigma(q, ln >> 4));
-        }
-    } else {
-        uint16_t *af = reinterpret_cast<uint16_t *>(sa);  // [piece][NS][64 lanes][8]
-        for (int e = tid; e < NS * 64 * 8; e += blockDim.x) {
-            const int el = e & 7, ln = (e >> 3) & 63, f = e >> 9;      // f = c * (KQ/8) + st
-            const int c = f / (KQ / 8), st = f % (KQ / 8);
-            const int row = 16 * c + (ln & 15), col = sigma(8 * st + el, ln >> 4);
-            if constexpr (MODE == 1) {
-                af[e] = adj ? P16[(size_t)col * N + row] : P16[(size_t)row * N + col];
-            } else {
-                uint16_t h, m, l;
-                split3(aval(row, col), h, m, l);
-                af[e] = h;
-                af[NS * 512 + e] = m;
-                af[2 * NS * 512 + e] = l;
-            }
-        }
+    // A operands: copy the plan's LDS image (built by k_stream_image)
+    {
+        const f4 *src = reinterpret_cast<const f4 *>(img);
+        f4 *dstl = reinterpret_cast<f4 *>(sa);
+        for (int e = tid; e < stream_lds_bytes<N, MODE>() / 16; e += blockDim.x) dstl[e] = src[e];
     }
     __syncthreads();
 
@@ -771,9 +788,43 @@ void launch_small(const dctplus_plan_s *p, const float *in, float *out, int64_t 
 
 }  // namespace
 
+// Streaming-kernel operand images (forward and adjoint) for folded plans with n <= 64.
+template <int N, int MODE>
+dctplus_status build_stream_image(dctplus_plan_s *p, hipStream_t s) {
+    constexpr size_t bytes = stream_lds_bytes<N, MODE>();
+    hipError_t e = hipMalloc(&p->simg, 2 * bytes);
+    if (e != hipSuccess) {
+        p->simg = nullptr;
+        (void)hipGetLastError();
+        return fail(DCTPLUS_ENOMEM, "hipMalloc for the streaming operand images failed");
+    }
+    p->simg_bytes = bytes;
+    unsigned char *img = (unsigned char *)p->simg;
+    for (int adj = 0; adj < 2; ++adj)
+        hipLaunchKernelGGL((k_stream_image<N, MODE>), dim3(16), dim3(256), 0, s, (const float *)p->t.mt32,
+                           (const uint16_t *)p->t.mt16, adj, img + adj * bytes);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "streaming operand images");
+    return DCTPLUS_OK;
+}
+
+dctplus_status stream_images(dctplus_plan_s *p, hipStream_t s) {
+    const int n = (int)p->n;
+    if (!p->t.folded || n < 16 || n > 64) return DCTPLUS_OK;
+    if (p->dtype == DCTPLUS_F32_SPLIT) return n == 32 ? build_stream_image<32, 2>(p, s) : build_stream_image<64, 2>(p, s);
+    if (p->dtype == DCTPLUS_BF16) return n == 32 ? build_stream_image<32, 1>(p, s) : build_stream_image<64, 1>(p, s);
+    if (p->dtype == DCTPLUS_F32) {
+        if (n == 16) return build_stream_image<16, 0>(p, s);
+        return n == 32 ? build_stream_image<32, 0>(p, s) : build_stream_image<64, 0>(p, s);
+    }
+    return DCTPLUS_OK;
+}
+
 void dense_release(dctplus_plan_s *p) {
     blaslt_release((BlasLtPlan *)p->blas);
     p->blas = nullptr;
+    if (p->simg) (void)hipFree(p->simg);
+    p->simg = nullptr;
 }
 
 dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s) {
@@ -832,7 +883,7 @@ dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s) {
                        (double *)nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "dense factor build");
-    return DCTPLUS_OK;
+    return stream_images(p, s);
 }
 
 dctplus_status dense_apply(dctplus_plan_s *p, const void *inv, void *outv, int64_t batch, bool adjoint,
@@ -880,11 +931,11 @@ dctplus_status dense_apply(dctplus_plan_s *p, const void *inv, void *outv, int64
             }
         } else {
             const int64_t ntiles = (batch + 15) / 16;
-            const float *P32 = p->t.mt32;
-            const uint16_t *P16 = p->t.mt16;
+            if (!p->simg) return fail(DCTPLUS_EDEVICE, "no streaming operand image on this plan");
+            const unsigned char *img = (const unsigned char *)p->simg + (adj ? p->simg_bytes : 0);
 #define DCTPLUS_STREAM(NN, MM)                                                                             \
     hipLaunchKernelGGL((k_dense_stream<NN, MM>), dim3(stream_blocks<NN, MM>(ntiles)), dim3(256), 0, s, in, out, \
-                       batch, P32, P16, adj)
+                       batch, img)
             if (split) {
                 if (n == 32) DCTPLUS_STREAM(32, 2);
                 else DCTPLUS_STREAM(64, 2);
