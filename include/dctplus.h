@@ -81,7 +81,8 @@ typedef struct {
     int32_t dtype;        /* dctplus_dtype */
     int32_t route;        /* dctplus_route */
     double defl_tol;      /* deflation threshold on |z_k| / ||z||; <= 0 selects 1e-13 */
-    int32_t nufft_width;  /* window taps of the sine NUFFT (FAST route), 4..16; 0 selects 12 */
+    int32_t nufft_width;  /* window taps of the sine NUFFT (FAST route), even, 4..16; 0 (the
+                             default) selects 12 for FP32 signals and 16 for FP64 */
     double direct_kappa;  /* FAST route: rows whose NUFFT error amplification exceeds this are
                              summed exactly in FP64; <= 0 selects 1e5 */
     int32_t device;       /* HIP device ordinal; < 0 uses the current device */

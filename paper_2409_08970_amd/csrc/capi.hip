@@ -86,7 +86,7 @@ void dctplus_default_opts(dctplus_opts *o) {
     o->dtype = DCTPLUS_F32;
     o->route = DCTPLUS_ROUTE_AUTO;
     o->defl_tol = 1e-13;
-    o->nufft_width = 12;
+    o->nufft_width = 0;   // chosen per dtype at plan time
     o->direct_kappa = 1e5;
     o->device = -1;
     o->factored = 0;
@@ -112,7 +112,8 @@ dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const d
         return fail(DCTPLUS_EINVAL, "bad route %d", o.route);
     if (!(o.defl_tol > 0.0)) o.defl_tol = 1e-13;
     if (!(o.direct_kappa > 0.0)) o.direct_kappa = 1e5;
-    if (o.nufft_width == 0) o.nufft_width = 12;
+    // window taps: 12 reach the FP32 bar, FP64 plans need 16 (error ~1e-14)
+    if (o.nufft_width == 0) o.nufft_width = (o.dtype == DCTPLUS_F64) ? 16 : 12;
     if (o.nufft_width < 4 || o.nufft_width > kMaxWidth || (o.nufft_width & 1))
         return fail(DCTPLUS_EINVAL, "nufft_width %d: must be even, 4..%d", o.nufft_width, kMaxWidth);
     int route = o.route;

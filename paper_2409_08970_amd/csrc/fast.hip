@@ -24,6 +24,11 @@
 // The DCT runs in the signal's precision (FP32 for FP32 plans); everything
 // from h onwards runs in FP64.  All per-signal work stays in LDS for
 // n <= 4096 (FP32); larger transforms keep the FP64 buffer in global scratch.
+// The placement is a template parameter, so every access to the buffer is an
+// LDS instruction or a global one and no address is ever generic: a generic
+// address formed below the start of the LDS window (a negative index folded
+// into the instruction's offset field) is not a legal address on the device,
+// even when address plus offset is.
 #include "fft.h"
 
 namespace dctplus {
@@ -31,7 +36,6 @@ namespace dctplus {
 namespace {
 
 constexpr int kExt = 16;      // grid extension on each side (>= max window half-width)
-constexpr bool fast_kernels_enabled = false;
 constexpr int kMaxPair = 16;  // register staging per thread in the grid post-processing
 
 __host__ __device__ inline int big_doubles(int n) {
@@ -56,10 +60,9 @@ __device__ __forceinline__ double grid_fold(const double *Gb, int p, int n) {
     return r <= 2 * n ? Gb[r] : -Gb[P - r];
 }
 
-template <typename TIO, typename TD>
+template <typename TIO, typename TD, bool kLds>
 __global__ void __launch_bounds__(1024) k_fast_fwd(PlanTables t, const TIO *__restrict__ x, TIO *__restrict__ y,
-                                                   int64_t batch, int nsig, int big_in_lds,
-                                                   double *__restrict__ gscratch) {
+                                                   int64_t batch, int nsig, double *__restrict__ gscratch) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = t.n, logn = t.logn, w = t.width, tid = threadIdx.x, nthr = blockDim.x;
     const int nd = t.ndirect;
@@ -67,9 +70,12 @@ __global__ void __launch_bounds__(1024) k_fast_fwd(PlanTables t, const TIO *__re
     const int ns = (int)((batch - s0) < nsig ? (batch - s0) : nsig);
     const int BD = big_doubles(n);
     const int logT = logn + 2;
-    double *big = big_in_lds ? reinterpret_cast<double *>(smem)
-                             : gscratch + (size_t)blockIdx.x * nsig * BD;
-    size_t off = big_in_lds ? sizeof(double) * (size_t)nsig * BD : 0;
+    double *big;
+    if constexpr (kLds)
+        big = reinterpret_cast<double *>(smem);
+    else
+        big = gscratch + (size_t)blockIdx.x * nsig * BD;
+    size_t off = kLds ? sizeof(double) * (size_t)nsig * BD : 0;
     TD *sd = reinterpret_cast<TD *>(smem + off);
     off += sizeof(TD) * (size_t)nsig * n;
     off = (off + 7) & ~size_t(7);
@@ -166,9 +172,12 @@ __global__ void __launch_bounds__(1024) k_fast_fwd(PlanTables t, const TIO *__re
     __syncthreads();
     for (int g = tid; g < ns * 2 * kExt; g += nthr) {
         const int s = g / (2 * kExt), e = g % (2 * kExt);
-        double *Ge = big + (size_t)s * BD + kExt;
-        const int p = e < kExt ? -(e + 1) : 2 * n + (e - kExt) + 1;
-        Ge[p] = grid_fold(Ge, p, n);
+        double *Gs = big + (size_t)s * BD;          // grid value G_p lives at Gs[kExt + p]
+        // gi = kExt + p for p = -1..-kExt and p = 2n+1..2n+kExt; kept opaque so that
+        // the compiler cannot split a negative part off into the offset field
+        int gi = e < kExt ? kExt - 1 - e : 2 * n + 1 + e;
+        asm volatile("" : "+v"(gi));
+        Gs[gi] = grid_fold(Gs + kExt, gi - kExt, n);
     }
 
     // 5. exact rows (isolated top root, ill-conditioned rows): one wave per (signal, row)
@@ -191,10 +200,12 @@ __global__ void __launch_bounds__(1024) k_fast_fwd(PlanTables t, const TIO *__re
         const TD *sds = sd + (size_t)s * n;
         double val;
         if (kind == ROW_NUFFT) {
-            const double *Ge = big + (size_t)s * BD + kExt + t.m0[ref];
+            int gi = kExt + t.m0[ref];                 // first tap, index >= 0 (m0 >= -kExt)
+            asm volatile("" : "+v"(gi));
+            const double *Gt = big + (size_t)s * BD + gi;
             const double *W = t.win + (size_t)ref * w;
             double acc = 0.0;
-            for (int q = 0; q < w; ++q) acc += W[q] * Ge[q];
+            for (int q = 0; q < w; ++q) acc += W[q] * Gt[q];
             val = t.rowA[ref] * acc + t.rowB[ref] * (double)sds[0];
         } else if (kind == ROW_DEFLATED) {
             val = (double)sds[ref];
@@ -205,10 +216,9 @@ __global__ void __launch_bounds__(1024) k_fast_fwd(PlanTables t, const TIO *__re
     }
 }
 
-template <typename TIO, typename TD>
+template <typename TIO, typename TD, bool kLds>
 __global__ void __launch_bounds__(1024) k_fast_adj(PlanTables t, const TIO *__restrict__ y, TIO *__restrict__ x,
-                                                   int64_t batch, int nsig, int big_in_lds,
-                                                   double *__restrict__ gscratch) {
+                                                   int64_t batch, int nsig, double *__restrict__ gscratch) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = t.n, logn = t.logn, w = t.width, tid = threadIdx.x, nthr = blockDim.x;
     const int nd = t.ndirect;
@@ -216,9 +226,12 @@ __global__ void __launch_bounds__(1024) k_fast_adj(PlanTables t, const TIO *__re
     const int ns = (int)((batch - s0) < nsig ? (batch - s0) : nsig);
     const int BD = big_doubles(n);
     const int logT = logn + 2;
-    double *big = big_in_lds ? reinterpret_cast<double *>(smem)
-                             : gscratch + (size_t)blockIdx.x * nsig * BD;
-    size_t off = big_in_lds ? sizeof(double) * (size_t)nsig * BD : 0;
+    double *big;
+    if constexpr (kLds)
+        big = reinterpret_cast<double *>(smem);
+    else
+        big = gscratch + (size_t)blockIdx.x * nsig * BD;
+    size_t off = kLds ? sizeof(double) * (size_t)nsig * BD : 0;
     TD *ry = reinterpret_cast<TD *>(smem + off);
     off += sizeof(TD) * (size_t)nsig * n;
     off = (off + 7) & ~size_t(7);
@@ -367,14 +380,21 @@ FastCfg fast_config(const dctplus_plan_s *p) {
     return c;
 }
 
+template <typename TIO, typename TD, bool kLds>
+void launch_fast(dctplus_plan_s *p, const FastCfg &c, dim3 grid, dim3 block, const void *in, void *out,
+                 int64_t batch, bool adjoint, double *scratch, hipStream_t s) {
+    if (!adjoint)
+        hipLaunchKernelGGL((k_fast_fwd<TIO, TD, kLds>), grid, block, c.lds, s, p->t, (const TIO *)in, (TIO *)out,
+                           batch, c.nsig, scratch);
+    else
+        hipLaunchKernelGGL((k_fast_adj<TIO, TD, kLds>), grid, block, c.lds, s, p->t, (const TIO *)in, (TIO *)out,
+                           batch, c.nsig, scratch);
+}
+
 }  // namespace
 
 dctplus_status fast_apply(dctplus_plan_s *p, const void *in, void *out, int64_t batch, bool adjoint,
                           hipStream_t s) {
-    // These kernels hit a GPU memory-aperture fault on their first MI355X run
-    // whose cause has not been identified; they stay switched off until it is.
-    if (!fast_kernels_enabled)
-        return fail(DCTPLUS_EUNSUPPORTED, "the FAST route kernels are switched off in this build");
     const FastCfg c = fast_config(p);
     const int n = (int)p->n;
     if ((size_t)c.nsig * n > (size_t)kMaxPair * c.threads)
@@ -390,19 +410,15 @@ dctplus_status fast_apply(dctplus_plan_s *p, const void *in, void *out, int64_t 
     if (blocks > 0x7fffffff) return fail(DCTPLUS_EINVAL, "batch too large");
     const dim3 grid((unsigned)blocks), block(c.threads);
     if (p->dtype == DCTPLUS_F64) {
-        if (!adjoint)
-            hipLaunchKernelGGL((k_fast_fwd<double, double>), grid, block, c.lds, s, p->t, (const double *)in,
-                               (double *)out, batch, c.nsig, (int)c.big_in_lds, scratch);
+        if (c.big_in_lds)
+            launch_fast<double, double, true>(p, c, grid, block, in, out, batch, adjoint, scratch, s);
         else
-            hipLaunchKernelGGL((k_fast_adj<double, double>), grid, block, c.lds, s, p->t, (const double *)in,
-                               (double *)out, batch, c.nsig, (int)c.big_in_lds, scratch);
+            launch_fast<double, double, false>(p, c, grid, block, in, out, batch, adjoint, scratch, s);
     } else {
-        if (!adjoint)
-            hipLaunchKernelGGL((k_fast_fwd<float, float>), grid, block, c.lds, s, p->t, (const float *)in,
-                               (float *)out, batch, c.nsig, (int)c.big_in_lds, scratch);
+        if (c.big_in_lds)
+            launch_fast<float, float, true>(p, c, grid, block, in, out, batch, adjoint, scratch, s);
         else
-            hipLaunchKernelGGL((k_fast_adj<float, float>), grid, block, c.lds, s, p->t, (const float *)in,
-                               (float *)out, batch, c.nsig, (int)c.big_in_lds, scratch);
+            launch_fast<float, float, false>(p, c, grid, block, in, out, batch, adjoint, scratch, s);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "fast route launch");

@@ -8,7 +8,8 @@
 // slot, and the consumers of an FFT read through it instead of paying for a
 // reordering pass.  Several independent signals (nsig, `stride` complex
 // elements apart) are transformed by one call.  The buffer may live in LDS or
-// in global scratch: the code only uses generic pointers and barriers.
+// in global scratch; callers pass pointers whose address space the compiler
+// can see through the inlining (LDS or global), never a generic one.
 #pragma once
 
 #include "common.h"

@@ -20,10 +20,6 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-FAST_SKIP = pytest.mark.skip(
-    reason="FAST-route kernels are switched off: their first GPU run raised a memory-aperture fault "
-           "whose cause is not yet identified; the library returns DCTPLUS_EUNSUPPORTED for them")
-
 TOL32 = 1e-5
 TOL64 = 1e-12
 TOLBF16 = 2e-2
@@ -125,7 +121,7 @@ def test_plan_spectrum_matches_oracle(n, kind):
     p.close()
 
 
-ROUTE_SIZES = [pytest.param("fast", n, marks=FAST_SKIP) for n in (4, 8, 16, 32, 64, 128, 256, 1024)] + \
+ROUTE_SIZES = [("fast", n) for n in (4, 8, 16, 32, 64, 128, 256, 1024)] + \
               [("dense", n) for n in (4, 8, 16, 32, 64, 128, 256)] + \
               [("gft", n) for n in (4, 8, 16, 32, 64, 128, 256)] + \
               [("dense-factored", n) for n in (4, 8, 16, 32, 64, 128, 256, 1024)]
@@ -148,7 +144,7 @@ def test_forward_and_adjoint_parity(route, n, kind):
     p.close()
 
 
-@pytest.mark.parametrize("route", [pytest.param("fast", marks=FAST_SKIP), "dense"])
+@pytest.mark.parametrize("route", ["fast", "dense"])
 @pytest.mark.parametrize("n", [1024, 4096, 16384])
 @pytest.mark.parametrize("kind", ["dense", "edge"])
 def test_large_n_full_batch_sampled(route, n, kind):
@@ -183,7 +179,7 @@ def test_large_n_full_batch_sampled(route, n, kind):
     del torch
 
 
-@pytest.mark.parametrize("route", [pytest.param("fast", marks=FAST_SKIP), "dense", "gft"])
+@pytest.mark.parametrize("route", ["fast", "dense", "gft"])
 def test_rho_zero_and_v_zero_give_dct2(route):
     import scipy.fft
     n = 64
@@ -196,7 +192,7 @@ def test_rho_zero_and_v_zero_give_dct2(route):
         p.close()
 
 
-@pytest.mark.parametrize("route", [pytest.param("fast", marks=FAST_SKIP), "dense", "gft"])
+@pytest.mark.parametrize("route", ["fast", "dense", "gft"])
 @pytest.mark.parametrize("n", [16, 64, 256])
 def test_double_eigenvalues_from_mirror_edge(route, n):
     """A mirror-symmetric added edge makes a secular root land on a deflated
@@ -211,7 +207,7 @@ def test_double_eigenvalues_from_mirror_edge(route, n):
     p.close()
 
 
-@pytest.mark.parametrize("route", [pytest.param("fast", marks=FAST_SKIP), "dense", "gft", "auto"])
+@pytest.mark.parametrize("route", ["fast", "dense", "gft", "auto"])
 def test_fp64_self_loop_dst7(route):
     """Workload 1: n = 64, unit self-loop at vertex 0, 1024 N(0,1) signals in FP64;
     the basis is the DST-VII closed form."""
@@ -289,7 +285,7 @@ def test_f32_split_bf16_products(route, n, kind):
     p.close()
 
 
-@pytest.mark.parametrize("route", [pytest.param("fast", marks=FAST_SKIP), "dense", "gft", "dense-f32split"])
+@pytest.mark.parametrize("route", ["fast", "dense", "gft", "dense-f32split"])
 def test_full_size_workload2_sampled(route):
     """Workload-2 launch shape (2^20 AR(0.95) signals, n = 64): every output
     row runs on the GPU; 2048 sampled signals are checked against Jacobi."""
@@ -340,8 +336,8 @@ def test_batch_edge_cases_and_errors():
         p.close()
 
 
-@pytest.mark.parametrize("route,n", [pytest.param("fast", 64, marks=FAST_SKIP),
-                                     pytest.param("fast", 4096, marks=FAST_SKIP), ("dense", 64), ("gft", 64),
+@pytest.mark.parametrize("route,n", [("fast", 64),
+                                     ("fast", 4096), ("dense", 64), ("gft", 64),
                                      ("dense", 1024), ("gft", 256)])
 def test_bitwise_determinism(route, n):
     torch = _torch()
@@ -374,7 +370,7 @@ def _gpu_grad(n, rho, v, x, route):
     return out
 
 
-@pytest.mark.parametrize("route", [pytest.param("fast", marks=FAST_SKIP), "dense", "gft"])
+@pytest.mark.parametrize("route", ["fast", "dense", "gft"])
 def test_gradient_n16_vs_oracle(route):
     n = 16
     W = workloads.workload5(n=n, batch=512)
