@@ -180,39 +180,65 @@ __global__ void __launch_bounds__(1024) k_fast_fwd(PlanTables t, const TIO *__re
         Gs[gi] = grid_fold(Gs + kExt, gi - kExt, n);
     }
 
-    // 5. exact rows (isolated top root, ill-conditioned rows): one wave per (signal, row)
+    // 5. exact rows (isolated top root, ill-conditioned rows): each (signal, row) pair
+    //    is split over wpp waves when there are fewer pairs than waves; the partial
+    //    sums are added in a fixed order
     const int wave = tid >> 6, lane = tid & 63, nwave = nthr >> 6;
-    for (int it = wave; it < ns * nd; it += nwave) {
-        const int s = it / nd, r = it % nd;
+    const int pairs = ns * nd;
+    const int wpp = (pairs > 0 && pairs < nwave) ? nwave / pairs : 1;
+    double *part = dres + (size_t)nsig * nd;   // [pairs * wpp <= nwave] partial sums
+    for (int it = wave; it < pairs * wpp; it += nwave) {
+        const int pr = it / wpp, c = it % wpp;
+        const int s = pr / nd, r = pr % nd;
         const double *D = t.direct + (size_t)r * n;
         const TD *sds = sd + (size_t)s * n;
         double acc = 0.0;
-        for (int j = lane; j < n; j += 64) acc += D[j] * (double)sds[j];
+        for (int j = c * 64 + lane; j < n; j += wpp * 64) acc += D[j] * (double)sds[j];
         acc = wave_sum(acc);
-        if (lane == 0) dres[(size_t)s * nd + r] = acc;
+        if (lane == 0) {
+            if (wpp == 1)
+                dres[pr] = acc;
+            else
+                part[it] = acc;
+        }
+    }
+    if (wpp > 1) {
+        __syncthreads();
+        for (int pr = tid; pr < pairs; pr += nthr) {
+            double acc = 0.0;
+            for (int c = 0; c < wpp; ++c) acc += part[pr * wpp + c];
+            dres[pr] = acc;
+        }
     }
     __syncthreads();
 
-    // 6. outputs in row order
+    // 6. outputs.  NUFFT rows in bin order: the per-bin tables are read directly (an
+    //    empty bin has zero weights and an in-range first tap), only the store needs
+    //    the row; then the deflated rows and the exact rows.
+    const int hw = w / 2;
+    for (int g = tid; g < ns * (n - 1); g += nthr) {
+        const int s = g / (n - 1), b = g % (n - 1);
+        const int row = t.rowOfBin[b];
+        // aligned taps start at grid point 2b + 1 - hw (closed form: no table lookup in the
+        // address); the row factor rowA is folded into the weights
+        int gi = kExt + 2 * b + 1 - hw;                // index >= kExt + 1 - hw > 0
+        asm volatile("" : "+v"(gi));
+        const double *Gt = big + (size_t)s * BD + gi;
+        const double *W = t.wina + (size_t)b * kTaps;
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < kTaps; ++k) acc += W[k] * Gt[k];   // fixed count: every load in flight
+        const double val = acc + t.rowB[b] * (double)sd[(size_t)s * n];
+        if (row >= 0) y[(s0 + s) * n + row] = (TIO)val;
+    }
     for (int g = tid; g < ns * n; g += nthr) {
-        const int s = g / n, i = g % n;
-        const int kind = t.kind[i], ref = t.ref[i];
-        const TD *sds = sd + (size_t)s * n;
-        double val;
-        if (kind == ROW_NUFFT) {
-            int gi = kExt + t.m0[ref];                 // first tap, index >= 0 (m0 >= -kExt)
-            asm volatile("" : "+v"(gi));
-            const double *Gt = big + (size_t)s * BD + gi;
-            const double *W = t.win + (size_t)ref * w;
-            double acc = 0.0;
-            for (int q = 0; q < w; ++q) acc += W[q] * Gt[q];
-            val = t.rowA[ref] * acc + t.rowB[ref] * (double)sds[0];
-        } else if (kind == ROW_DEFLATED) {
-            val = (double)sds[ref];
-        } else {
-            val = dres[(size_t)s * nd + ref];
-        }
-        y[(s0 + s) * n + i] = (TIO)val;
+        const int s = g / n, k = g % n;
+        const int row = t.rowOfK[k];
+        if (row >= 0) y[(s0 + s) * n + row] = (TIO)(double)sd[(size_t)s * n + k];
+    }
+    for (int g = tid; g < ns * nd; g += nthr) {
+        const int s = g / nd, r = g % nd;
+        y[(s0 + s) * n + t.direct_row[r]] = (TIO)dres[g];
     }
 }
 
@@ -232,57 +258,95 @@ __global__ void __launch_bounds__(1024) k_fast_adj(PlanTables t, const TIO *__re
     else
         big = gscratch + (size_t)blockIdx.x * nsig * BD;
     size_t off = kLds ? sizeof(double) * (size_t)nsig * BD : 0;
-    TD *ry = reinterpret_cast<TD *>(smem + off);
+    TD *yb = reinterpret_cast<TD *>(smem + off);   // input rows in bin order (0 for empty bins)
     off += sizeof(TD) * (size_t)nsig * n;
     off = (off + 7) & ~size_t(7);
     double *sd0 = reinterpret_cast<double *>(smem + off);
     const cplx<TD> *twd = reinterpret_cast<const cplx<TD> *>(sizeof(TD) == 8 ? (const void *)t.tw64
                                                                              : (const void *)t.tw32);
-    for (int g = tid; g < ns * n; g += nthr) ry[g] = (TD)y[s0 * n + g];
+    // the NUFFT rows of the input, gathered once into bin order: every later read of
+    // them is then a plain LDS read with no table lookup in its address
+    for (int g = tid; g < ns * n; g += nthr) {
+        const int s = g / n, b = g % n;
+        const int r = (b < n - 1) ? t.rowOfBin[b] : -1;
+        yb[g] = (r >= 0) ? (TD)y[(s0 + s) * n + r] : (TD)0;
+    }
     __syncthreads();
 
-    // transpose of the s_0 / mu compensation: sd0 = sum_b rowB_b y_row(b)
+    // transpose of the s_0 / mu compensation: sd0 = sum_b rowB_b y_row(b); each signal's
+    // sum is split over wps waves, the partial sums added in a fixed order
     const int wave = tid >> 6, lane = tid & 63, nwave = nthr >> 6;
-    for (int s = wave; s < ns; s += nwave) {
+    const int wps = ns < nwave ? nwave / ns : 1;
+    double *part = sd0 + nsig;   // [ns * wps <= nwave] partial sums
+    for (int it = wave; it < ns * wps; it += nwave) {
+        const int s = it / wps, c = it % wps;
         double acc = 0.0;
-        for (int b = lane; b < n - 1; b += 64) {
-            const int r = t.rowOfBin[b];
-            if (r >= 0) acc += t.rowB[b] * (double)ry[(size_t)s * n + r];
-        }
+        for (int b = c * 64 + lane; b < n - 1; b += wps * 64) acc += t.rowB[b] * (double)yb[(size_t)s * n + b];
         acc = wave_sum(acc);
-        if (lane == 0) sd0[s] = acc;
+        if (lane == 0) {
+            if (wps == 1)
+                sd0[s] = acc;
+            else
+                part[it] = acc;
+        }
     }
 
-    // transpose of the interpolation: spread u_b = rowA_b y_row(b) onto the grid
-    // (gather form), folded back onto G'_1..G'_{2n-1}, then written as the odd
-    // extension of length 4n for the grid DST-I
+    // transpose of the interpolation: spread u_b = rowA_b y_row(b) onto the grid in
+    // gather form, folded back onto G'_1..G'_{2n-1}, then written as the odd extension
+    // of length 4n for the grid DST-I.  Bin b reaches grid points 2b + 1 - hw + k,
+    // k < w + 2, through the aligned weights (rowA folded in), so the loads of a grid
+    // point's bins do not depend on one another; the fold terms G(-p) and G(4n - p)
+    // are nonzero only within hw of the two ends.
     const int hw = w / 2;
-    auto gather = [&](int s, int p) -> double {
-        int blo = (p - 1 - hw + 1) >> 1;   // ceil((p - 1 - hw) / 2)
-        int bhi = (p - 1 + hw) >> 1;
+    auto gather = [&](int s, int P) -> double {
+        int blo = ((P - hw - 3) >> 1) + 1;   // bins with 0 <= P - (2b + 1 - hw) < w + 2
+        int bhi = (P - 1 + hw) >> 1;
         if (blo < 0) blo = 0;
         if (bhi > n - 2) bhi = n - 2;
+        asm volatile("" : "+v"(blo));        // keep the first bin whole (no negative part in the base)
         double acc = 0.0;
-        for (int b = blo; b <= bhi; ++b) {
-            const int r = t.rowOfBin[b];
-            if (r < 0) continue;
-            const int q = p - t.m0[b];
-            if (q < 0 || q >= w) continue;
-            acc += t.win[(size_t)b * w + q] * t.rowA[b] * (double)ry[(size_t)s * n + r];
+        // at most kTaps / 2 + 1 bins reach a grid point: a fixed, predicated count
+#pragma unroll
+        for (int k = 0; k < kTaps / 2 + 1; ++k) {
+            const int b = blo + k;
+            if (b <= bhi) acc += t.wina[(size_t)b * kTaps + (P - 2 * b - 1 + hw)] * (double)yb[(size_t)s * n + b];
         }
         return acc;
     };
-    for (int g = tid; g < ns * 2 * n; g += nthr) {
-        const int s = g / (2 * n), p = g % (2 * n);
-        double *q = big + (size_t)s * BD;
-        if (p == 0) {
-            q[0] = 0.0;
-            q[2 * n] = 0.0;
-            continue;
+    // two grid points per thread and iteration, so that the loads of both are in flight together
+    for (int g0 = tid; g0 < ns * 2 * n; g0 += 2 * nthr) {
+        double Gv[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int g = g0 + h * nthr;
+            const int s = g / (2 * n), p = g % (2 * n);
+            Gv[h] = (g < ns * 2 * n && p != 0) ? gather(s, p) : 0.0;
         }
-        const double G = gather(s, p) - gather(s, -p) - gather(s, 4 * n - p);
-        q[p] = G;
-        q[4 * n - p] = -G;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int g = g0 + h * nthr;
+            if (g >= ns * 2 * n) break;
+            const int s = g / (2 * n), p = g % (2 * n);
+            double *q = big + (size_t)s * BD;
+            if (p == 0) {
+                q[0] = 0.0;
+                q[2 * n] = 0.0;
+                continue;
+            }
+            double G = Gv[h];
+            if (p <= hw) G -= gather(s, -p);
+            if (p >= 2 * n - hw) G -= gather(s, 4 * n - p);
+            q[p] = G;
+            q[4 * n - p] = -G;
+        }
+    }
+    if (wps > 1) {
+        __syncthreads();
+        for (int s = tid; s < ns; s += nthr) {
+            double acc = 0.0;
+            for (int c = 0; c < wps; ++c) acc += part[s * wps + c];
+            sd0[s] = acc;
+        }
     }
     __syncthreads();
     cplx<double> *Bc = reinterpret_cast<cplx<double> *>(big);
@@ -327,9 +391,10 @@ __global__ void __launch_bounds__(1024) k_fast_adj(PlanTables t, const TIO *__re
     for (int g = tid; g < ns * n; g += nthr) {
         const int s = g / n, j = g % n;
         double v = (j == 0) ? sd0[s] : t.hz[j] * dst1_post(Bc + (size_t)s * strideB, j, logn, rpB, t.tw64, logT);
+        const TIO *ys = y + (s0 + s) * n;   // deflated and exact rows come straight from the input
         const int rk = t.rowOfK[j];
-        if (rk >= 0) v += (double)ry[(size_t)s * n + rk];
-        for (int r = 0; r < nd; ++r) v += t.direct[(size_t)r * n + j] * (double)ry[(size_t)s * n + t.direct_row[r]];
+        if (rk >= 0) v += (double)(TD)ys[rk];
+        for (int r = 0; r < nd; ++r) v += t.direct[(size_t)r * n + j] * (double)(TD)ys[t.direct_row[r]];
         big[(size_t)s * BD + 2 * n + j] = v;
     }
     __syncthreads();
@@ -376,7 +441,7 @@ FastCfg fast_config(const dctplus_plan_s *p) {
     while (ns > 1 && (size_t)ns * n > (size_t)kMaxPair * c.threads) ns >>= 1;
     while (ns > 1 && (size_t)ns * ((c.big_in_lds ? per_big : 0) + per_small) > budget) ns >>= 1;
     c.nsig = ns;
-    c.lds = (size_t)ns * ((c.big_in_lds ? per_big : 0) + per_small) + 64;
+    c.lds = (size_t)ns * ((c.big_in_lds ? per_big : 0) + per_small) + 64 + 8 * 16;   // + exact-row partials
     return c;
 }
 

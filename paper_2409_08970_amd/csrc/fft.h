@@ -80,9 +80,10 @@ __device__ __forceinline__ void dft_reg(cplx<T> *x) {
 }
 
 // Sequence of pass radices for an N = 2^logN transform of nsig signals on
-// nthreads threads: radix 16 while every thread still gets a butterfly,
-// smaller radices otherwise.  Must be computed identically by the FFT and by
-// whoever reads its output.
+// nthreads threads: radix 16 while at least two waves' worth of butterflies
+// remain (a pass costs a barrier and a round of memory latency, so fewer,
+// wider passes win once the transform is small), smaller radices otherwise.
+// Must be computed identically by the FFT and by whoever reads its output.
 struct RadixPlan {
     int np;          // number of passes
     uint32_t code;   // 2 bits per pass: log2(radix) - 1
@@ -96,7 +97,7 @@ __device__ __forceinline__ RadixPlan radix_plan(int logN, int nsig, int nthreads
     int rem = logN;
     while (rem > 0) {
         int lr = rem < 4 ? rem : 4;
-        while (lr > 1 && (nsig << (logN - lr)) < nthreads) --lr;
+        while (lr > 1 && (nsig << (logN - lr)) < (nthreads < 128 ? nthreads : 128)) --lr;
         rp.code |= (uint32_t)(lr - 1) << (2 * rp.np);
         ++rp.np;
         rem -= lr;

@@ -280,6 +280,7 @@ __global__ void __launch_bounds__(kPlanThreads) k_rows(PlanTables t, const int32
         t.rowB[i] = 0.0;
         t.m0[i] = 2 * i + 1 - w / 2;
         for (int q = 0; q < w; ++q) t.win[(size_t)i * w + q] = 0.0;
+        for (int k = 0; k < kTaps; ++k) t.wina[(size_t)i * kTaps + k] = 0.0;
     }
     __syncthreads();
 
@@ -328,6 +329,13 @@ __global__ void __launch_bounds__(kPlanThreads) k_rows(PlanTables t, const int32
                 t.rowB[b] = a * t.z[0] / mu;
                 t.m0[b] = m0;
                 for (int q = 0; q < w; ++q) t.win[(size_t)b * w + q] = es_window(x - (m0 + q), w, beta);
+                // the same taps on the aligned origin 2b + 1 - w/2 (m0 is that origin or the next point)
+                const int sh = m0 - (2 * b + 1 - w / 2);
+                for (int k = 0; k < w + 2; ++k) {
+                    const int q = k - sh;
+                    t.wina[(size_t)b * kTaps + k] =
+                        (q >= 0 && q < w) ? t.rowA[b] * es_window(x - (m0 + q), w, beta) : 0.0;
+                }
                 rowOfBin[b] = row;
                 t.kind[row] = ROW_NUFFT;
                 t.ref[row] = b;
@@ -448,7 +456,7 @@ dctplus_status plan_build(dctplus_plan_s *p, const double *v_host, hipStream_t s
         {(void **)&t.z, nd}, {(void **)&t.zraw, nd}, {(void **)&t.mu, nd}, {(void **)&t.a, nd}, {(void **)&t.origin, ni},
         {(void **)&t.tau, nd}, {(void **)&t.kind, ni}, {(void **)&t.ref, ni}, {(void **)&t.hz, nd},
         {(void **)&t.deconv, nd}, {(void **)&t.rowA, nd}, {(void **)&t.rowB, nd}, {(void **)&t.m0, ni},
-        {(void **)&t.win, nd * w}, {(void **)&t.direct_row, sizeof(int32_t) * kMaxDirect},
+        {(void **)&t.win, nd * w}, {(void **)&t.wina, nd * kTaps}, {(void **)&t.direct_row, sizeof(int32_t) * kMaxDirect},
         {(void **)&t.tw64, sizeof(cplx<double>) * 4 * n}, {(void **)&t.tw32, sizeof(cplx<float>) * 4 * n},
         {(void **)&t.sintab, sizeof(double) * (2 * n + 1)}, {(void **)&t.status, sizeof(int32_t) * 8},
         {(void **)&rowOfBin, ni}, {(void **)&rowOfK, ni},
