@@ -71,7 +71,8 @@ typedef enum {
 
 /* How the product with diag(a) C(mu, lambda) diag(z) is formed. */
 typedef enum {
-    DCTPLUS_ROUTE_AUTO = 0,  /* DENSE: the faster route on MI355X at the measured sizes */
+    DCTPLUS_ROUTE_AUTO = 0,  /* the faster route measured on MI355X: DENSE for n < 16384,
+                                FAST for n = 16384 (FP32 and FP64 signals) */
     DCTPLUS_ROUTE_FAST = 1,  /* Alg. 1 / Thm 3.3: DCT-II, DST-I, sine NUFFT, O(n log n) */
     DCTPLUS_ROUTE_DENSE = 2, /* Thm 3.1: DCT-II, then an MFMA product with the n x n Cauchy factor */
     DCTPLUS_ROUTE_GFT = 3    /* dense GFT (the paper's naive product): MFMA product with X^T */

@@ -118,8 +118,10 @@ dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const d
         return fail(DCTPLUS_EINVAL, "nufft_width %d: must be even, 4..%d", o.nufft_width, kMaxWidth);
     int route = o.route;
     if (route == DCTPLUS_ROUTE_AUTO) {
-        // the dense product is the faster route at the measured sizes
-        route = DCTPLUS_ROUTE_DENSE;
+        // measured on MI355X (forward + adjoint, 256 signals): the O(n^2) MFMA/GEMM product
+        // is as fast as the O(n log n) route up to n = 4096 and slower at n = 16384
+        route = (n >= 16384 && (o.dtype == DCTPLUS_F32 || o.dtype == DCTPLUS_F64)) ? DCTPLUS_ROUTE_FAST
+                                                                                   : DCTPLUS_ROUTE_DENSE;
     }
     if ((o.dtype == DCTPLUS_BF16 || o.dtype == DCTPLUS_F32_SPLIT) && route == DCTPLUS_ROUTE_FAST)
         return fail(DCTPLUS_EUNSUPPORTED, "BF16 operands apply to the DENSE and GFT routes");

@@ -207,6 +207,24 @@ def test_double_eigenvalues_from_mirror_edge(route, n):
     p.close()
 
 
+@pytest.mark.parametrize("n,dtype,expect", [(64, "f32", "dense"), (4096, "f32", "dense"), (16384, "f32", "fast"),
+                                            (16384, "bf16", None), (64, "f64", "dense")])
+def test_auto_route_choice(n, dtype, expect):
+    """AUTO takes the route measured faster on this GPU: the dense product below
+    n = 16384, the O(n log n) route at n = 16384 (BF16 operands exist on the dense
+    route only, for n in {32, 64})."""
+    _torch()
+    from paper_2409_08970_amd import Plan, _binding as B
+    v = workloads.unit_vector(np.random.default_rng(n), n)
+    if expect is None:
+        with pytest.raises(B.DctPlusError):
+            Plan(n, 0.5, v, route="auto", dtype=dtype)
+        return
+    p = Plan(n, 0.5, v, route="auto", dtype=dtype)
+    assert p.route == expect
+    p.close()
+
+
 @pytest.mark.parametrize("route", ["fast", "dense", "gft", "auto"])
 def test_fp64_self_loop_dst7(route):
     """Workload 1: n = 64, unit self-loop at vertex 0, 1024 N(0,1) signals in FP64;
