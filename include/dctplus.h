@@ -85,7 +85,8 @@ typedef struct {
     int32_t nufft_width;  /* window taps of the sine NUFFT (FAST route), even, 4..16; 0 (the
                              default) selects 12 for FP32 signals and 16 for FP64 */
     double direct_kappa;  /* FAST route: rows whose NUFFT error amplification exceeds this are
-                             summed exactly in FP64; <= 0 selects 1e5 */
+                             summed exactly in FP64; <= 0 (the default) selects 1e5 for FP32
+                             signals and 1e3 for FP64 */
     int32_t device;       /* HIP device ordinal; < 0 uses the current device */
     int32_t factored;     /* DENSE route only, F32 or BF16: 1 keeps the two factors of Thm 3.1
                              apart (a DCT-II of every signal, then the product with the Cauchy

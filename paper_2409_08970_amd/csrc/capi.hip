@@ -87,7 +87,7 @@ void dctplus_default_opts(dctplus_opts *o) {
     o->route = DCTPLUS_ROUTE_AUTO;
     o->defl_tol = 1e-13;
     o->nufft_width = 0;   // chosen per dtype at plan time
-    o->direct_kappa = 1e5;
+    o->direct_kappa = 0.0;   // chosen per dtype at plan time
     o->device = -1;
     o->factored = 0;
 }
@@ -111,7 +111,9 @@ dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const d
     if (o.route < DCTPLUS_ROUTE_AUTO || o.route > DCTPLUS_ROUTE_GFT)
         return fail(DCTPLUS_EINVAL, "bad route %d", o.route);
     if (!(o.defl_tol > 0.0)) o.defl_tol = 1e-13;
-    if (!(o.direct_kappa > 0.0)) o.direct_kappa = 1e5;
+    // exact-row threshold on the NUFFT error amplification: 1e5 keeps FP32 plans within
+    // 1e-6; FP64 plans take rows amplifying the window error by more than 1e3 exactly
+    if (!(o.direct_kappa > 0.0)) o.direct_kappa = (o.dtype == DCTPLUS_F64) ? 1e3 : 1e5;
     // window taps: 12 reach the FP32 bar, FP64 plans need 16 (error ~1e-14)
     if (o.nufft_width == 0) o.nufft_width = (o.dtype == DCTPLUS_F64) ? 16 : 12;
     if (o.nufft_width < 4 || o.nufft_width > kMaxWidth || (o.nufft_width & 1))

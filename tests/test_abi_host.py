@@ -49,7 +49,7 @@ def test_status_strings_and_defaults(lib):
     assert B.dctplus_status_string(99) == "unknown status"
     o = B.dctplus_default_opts()
     assert (o.dtype, o.route, o.nufft_width, o.device, o.factored) == (0, 0, 0, -1, 0)
-    assert o.defl_tol == 1e-13 and o.direct_kappa == 1e5
+    assert o.defl_tol == 1e-13 and o.direct_kappa == 0.0   # 0: chosen per dtype at plan time
 
 
 @pytest.mark.parametrize("n,rho,vfill,expect", [

@@ -244,6 +244,29 @@ def test_fp64_self_loop_dst7(route):
     p.close()
 
 
+TOL_FAST64 = 1e-11
+
+
+@pytest.mark.parametrize("n,batch", [(8, 75), (64, 75), (256, 75), (1024, 20), (4096, 4)])
+@pytest.mark.parametrize("kind", ["dense", "loopn", "edge", "negative"])
+def test_fp64_fast_parity(n, batch, kind):
+    """FP64 signals on the FAST route.  Thm 3.3 is exact up to the NUFFT error: 16
+    window taps leave ~1e-15 per interpolated value, and rows that would amplify it
+    by more than 1e3 (small sin(n psi)) are summed exactly, so the bar is 1e-11
+    against the secular semi-oracle (1e-12 for the dense routes)."""
+    rho, v = case(n, kind)
+    g = np.random.default_rng(5 * n + 3)
+    x = g.standard_normal((batch, n))
+    yin = g.standard_normal((batch, n))
+    p = make_plan(n, rho, v, "fast", dtype="f64")
+    y = run(p, x)
+    xa = run(p, yin, adjoint=True)
+    p.close()
+    sp = oracle.semi_plan(n, rho, v)
+    assert relerr(y, oracle.semi_forward(n, rho, v, x, sp)) <= TOL_FAST64, (n, kind)
+    assert relerr(xa, oracle.semi_adjoint(n, rho, v, yin, sp)) <= TOL_FAST64, (n, kind)
+
+
 @pytest.mark.parametrize("route", ["dense", "gft"])
 @pytest.mark.parametrize("n", [4, 8, 16, 32, 64, 128, 256, 1024])
 @pytest.mark.parametrize("kind", ["dense", "loopn", "edge", "negative"])
