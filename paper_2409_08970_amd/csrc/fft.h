@@ -139,9 +139,36 @@ __device__ __forceinline__ void fft_pass(cplx<T> *buf, int nsig, int stride, int
         for (int r = 0; r < R; ++r) x[r] = base[r << logm];
         dft_reg<LR>(x);
         if (logm > 0) {
+            // twiddles w^r, w = exp(-2 pi i j / L): w, w^4 and w^8 come from the table and
+            // the rest from at most three products (w^r = w^(r mod 4) w^(r - r mod 4)), so a
+            // radix-16 butterfly reads 3 table entries instead of 15 (the table reads,
+            // shared by every workgroup through L2, bounded the passes at large n)
             const int sh = logNtw - logL;
+            const cplx<T> w1 = tw[j << sh];
+            if constexpr (R == 2) {
+                x[1] = cmul(x[1], w1);
+            } else {
+                const cplx<T> w2 = cmul(w1, w1);
+                const cplx<T> lo[4] = {cplx<T>{T(1), T(0)}, w1, w2, cmul(w2, w1)};
+                if constexpr (R == 4) {
 #pragma unroll
-            for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[(j * r) << sh]);
+                    for (int r = 1; r < 4; ++r) x[r] = cmul(x[r], lo[r]);
+                } else {
+                    const cplx<T> w4 = tw[(4 * j) << sh];
+                    cplx<T> hi[4] = {cplx<T>{T(1), T(0)}, w4, w4, w4};
+                    if constexpr (R == 16) {
+                        const cplx<T> w8 = tw[(8 * j) << sh];
+                        hi[2] = w8;
+                        hi[3] = cmul(w8, w4);
+                    }
+#pragma unroll
+                    for (int r = 1; r < R; ++r) {
+                        const cplx<T> wr = (r >> 2) == 0 ? lo[r & 3]
+                                           : ((r & 3) == 0 ? hi[r >> 2] : cmul(lo[r & 3], hi[r >> 2]));
+                        x[r] = cmul(x[r], wr);
+                    }
+                }
+            }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) base[r << logm] = x[r];
