@@ -312,6 +312,9 @@ def main():
                                      max(3, args.steps // 4), 2)
                 large[rt] = {"ms_per_step": t3, "value": 256 * nl / (t3 * 1e-3)}
                 p3.close()
+            pa = Plan(nl, W3["rho"], W3["v"], route="auto")
+            large["dct_plus_auto"] = {"route": pa.route, **large[pa.route]}
+            pa.close()
             A = torch.randn(nl, nl, device=dev)
             At = A.t().contiguous()
             t3, _, _ = time_pair(torch, lambda: torch.matmul(x3, A, out=y3), lambda: torch.matmul(y3, At, out=r3),

@@ -120,10 +120,10 @@ dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const d
         return fail(DCTPLUS_EINVAL, "nufft_width %d: must be even, 4..%d", o.nufft_width, kMaxWidth);
     int route = o.route;
     if (route == DCTPLUS_ROUTE_AUTO) {
-        // measured on MI355X (forward + adjoint, 256 signals): the O(n^2) MFMA/GEMM product
-        // is as fast as the O(n log n) route up to n = 4096 and slower at n = 16384
-        route = (n >= 16384 && (o.dtype == DCTPLUS_F32 || o.dtype == DCTPLUS_F64)) ? DCTPLUS_ROUTE_FAST
-                                                                                   : DCTPLUS_ROUTE_DENSE;
+        // measured on MI355X (forward + adjoint, FP32): the O(n^2) MFMA/GEMM product wins up
+        // to n = 1024, the O(n log n) route from n = 4096 on.  FP64 plans stay on the dense
+        // product, which is exact to 1e-12 (the FAST route to ~1e-11, its window error)
+        route = (n >= 4096 && o.dtype == DCTPLUS_F32) ? DCTPLUS_ROUTE_FAST : DCTPLUS_ROUTE_DENSE;
     }
     if ((o.dtype == DCTPLUS_BF16 || o.dtype == DCTPLUS_F32_SPLIT) && route == DCTPLUS_ROUTE_FAST)
         return fail(DCTPLUS_EUNSUPPORTED, "BF16 operands apply to the DENSE and GFT routes");
