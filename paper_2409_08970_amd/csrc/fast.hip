@@ -305,11 +305,18 @@ __global__ void __launch_bounds__(1024) k_fast_adj(PlanTables t, const TIO *__re
         if (bhi > n - 2) bhi = n - 2;
         asm volatile("" : "+v"(blo));        // keep the first bin whole (no negative part in the base)
         double acc = 0.0;
-        // at most kTaps / 2 + 1 bins reach a grid point: a fixed, predicated count
+        // at most kTaps / 2 + 1 bins reach a grid point: a fixed count of unconditional
+        // loads at clamped (valid) indices, the bins past bhi masked out by a select
 #pragma unroll
         for (int k = 0; k < kTaps / 2 + 1; ++k) {
             const int b = blo + k;
-            if (b <= bhi) acc += t.wina[(size_t)b * kTaps + (P - 2 * b - 1 + hw)] * (double)yb[(size_t)s * n + b];
+            const bool ok = b <= bhi;
+            int bb = ok ? b : blo;
+            bb = bb < n - 1 ? bb : n - 1;             // tables have n rows (row n - 1 is zero)
+            int tap = P - 2 * bb - 1 + hw;
+            tap = tap < 0 ? 0 : (tap > kTaps - 1 ? kTaps - 1 : tap);
+            const double c = t.wina[(size_t)bb * kTaps + tap] * (double)yb[(size_t)s * n + bb];
+            acc += ok ? c : 0.0;
         }
         return acc;
     };
