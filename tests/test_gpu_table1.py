@@ -3,9 +3,9 @@ implementation against the dense product, for the three updated path graphs of
 Fig. 3 at n = 8 .. 256 on AR(0.99) signals.
 
 The paper's numbers (tests/golden/table1_snr.txt) are the accuracy of its fast
-FP64 route; our FP64 dense route must exceed every one of them against the
-Jacobi oracle, and the FP32 route must exceed the paper's 100 dB claim (the
-1e-5 relative-error bar).  Graph readings (0-based vertices, alpha = 1.5):
+FP64 route; our FP64 routes (the fast one of Alg. 1 and the dense one) must
+exceed every one of them against the Jacobi oracle, and the FP32 routes must
+exceed the paper's 100 dB claim (the 1e-5 relative-error bar).  Graph readings (0-based vertices, alpha = 1.5):
 SLA: self-loop of weight alpha at vertex 0 (rho = 1.5, v = e_0); EU: the edge
 (1, 2) takes weight alpha instead of 1 (rho = 2 (alpha - 1) = 1,
 v = (e_1 - e_2)/sqrt 2); EA: added edge (2, 4) of weight alpha (rho = 3,
@@ -55,9 +55,10 @@ def test_golden_table_is_the_papers():
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("route", ["fast", "dense"])
 @pytest.mark.parametrize("kind", ["EU", "SLA", "EA"])
 @pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 256])
-def test_snr_floor(kind, n):
+def test_snr_floor(kind, n, route):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -67,13 +68,13 @@ def test_snr_floor(kind, n):
     x = workloads.ar1(np.random.default_rng(4000 + n), 2000, n, 0.99, dtype=np.float64)
     _, X = oracle.basis(n, rho, v)
     yref = oracle.forward(X, x)
-    p64 = Plan(n, rho, v, route="dense", dtype="f64")
+    p64 = Plan(n, rho, v, route=route, dtype="f64")
     y64 = p64.forward(torch.from_numpy(x).cuda()).cpu().numpy()
     p64.close()
-    p32 = Plan(n, rho, v, route="dense", dtype="f32")
+    p32 = Plan(n, rho, v, route=route, dtype="f32")
     y32 = p32.forward(torch.from_numpy(x.astype(np.float32)).cuda()).cpu().double().numpy()
     p32.close()
     s64, s32 = _snr(y64, yref), _snr(y32, yref)
-    print(f"{kind} n={n}: FP64 {s64:.1f} dB, FP32 {s32:.1f} dB (paper {floor} dB)")
-    assert s64 >= floor, (kind, n, s64, floor)
-    assert s32 >= 100.0, (kind, n, s32)
+    print(f"{route} {kind} n={n}: FP64 {s64:.1f} dB, FP32 {s32:.1f} dB (paper {floor} dB)")
+    assert s64 >= floor, (route, kind, n, s64, floor)
+    assert s32 >= 100.0, (route, kind, n, s32)
