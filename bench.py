@@ -122,6 +122,7 @@ def bench_selection(torch, dev, steps, warmup):
     plan_ms = (time.perf_counter() - t0) * 1e3
     x = torch.from_numpy(W["x"]).to(dev)
     y = torch.empty_like(x)
+    chosen, tune_ms = sel.tune(x)      # launch autotuner: persistent workgroups per CU
     for _ in range(warmup):
         sel.select(x, out=y)
     torch.cuda.synchronize()
@@ -145,6 +146,7 @@ def bench_selection(torch, dev, steps, warmup):
             "kernel": "k_select (persistent, FP32 MFMA)", "ms_per_pass": ms, "blocks_per_s": len(nb) / (ms * 1e-3),
             "signal_samples_per_s": samples / (ms * 1e-3), "pruned_fraction": pruned / (len(nb) * S),
             "plan_ms_host": plan_ms,
+            "autotune": {"workgroups_per_cu": chosen, "ms_per_pass_by_candidate": tune_ms},
             "roofline": {"mfma_tflops": flops / (ms * 1e-3) / 1e12, "mfma_peak_tflops": 157.3,
                          "hbm_gbs": bytes_ / (ms * 1e-3) / 1e9, "hbm_peak_gbs": HBM_PEAK_GBS,
                          "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": bytes_}}

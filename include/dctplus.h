@@ -196,6 +196,14 @@ void dctplus_plan_destroy(dctplus_plan_t plan);
  *   Asynchronous on `stream`; one persistent kernel launch.  Calls on one
  *   selection plan must not overlap (they share its work-queue counter).
  *
+ * dctplus_select_tune: the launch autotuner of dctplus_select.  Runs the
+ *   selection with the persistent grid at 1, 2, 3 and 4 workgroups per CU
+ *   (one warm-up and three timed calls each, HIP events on `stream`), keeps
+ *   the fastest in the plan for later dctplus_select calls, writes it to
+ *   *chosen (nullable) and the average milliseconds per call of each
+ *   candidate to ms[0..3] (HOST, nullable).  Arguments and errors as for
+ *   dctplus_select; the outputs hold the (grid-independent) result of the
+ *   last call.  Synchronises `stream`; not for use under graph capture.
  * dctplus_select_factor: HOST copy (n_b x n_b doubles, row-major, the FP32
  *   values as stored) of candidate r's factor of block `block`; synchronous.
  * dctplus_select_size: total floats of x / y_best (-1 for a NULL plan).
@@ -207,6 +215,9 @@ dctplus_status dctplus_select_plan(int64_t nblocks, int32_t K, int32_t S, const 
                                    const double *cand_host, void *stream, dctplus_select_t *out);
 dctplus_status dctplus_select(dctplus_select_t plan, const float *x, int32_t c_p, double prune_tau, int32_t *best,
                               float *cost, float *y_best, void *stream);
+dctplus_status dctplus_select_tune(dctplus_select_t plan, const float *x, int32_t c_p, double prune_tau,
+                                   int32_t *best, float *cost, float *y_best, void *stream, int32_t *chosen,
+                                   float *ms);
 dctplus_status dctplus_select_factor(dctplus_select_t plan, int64_t block, int32_t r, double *dst);
 int64_t dctplus_select_size(dctplus_select_t plan);
 void dctplus_select_destroy(dctplus_select_t plan);

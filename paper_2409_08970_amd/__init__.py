@@ -21,13 +21,13 @@ from . import _binding as B
 from ._binding import (DctPlusError, dctplus_adjoint, dctplus_default_opts, dctplus_forward, dctplus_grad,
                        dctplus_last_error, dctplus_plan, dctplus_plan_destroy, dctplus_plan_info,
                        dctplus_plan_table, dctplus_select, dctplus_select_destroy, dctplus_select_factor,
-                       dctplus_select_plan, dctplus_select_size, dctplus_status_string)
+                       dctplus_select_plan, dctplus_select_size, dctplus_select_tune, dctplus_status_string)
 
 __all__ = [
     "Plan", "DctPlusFn", "dctplus", "DctPlusError", "dctplus_plan", "dctplus_forward", "dctplus_adjoint",
     "dctplus_grad", "dctplus_plan_info", "dctplus_plan_table", "dctplus_plan_destroy", "dctplus_status_string",
     "dctplus_last_error", "dctplus_default_opts", "SelectPlan", "dctplus_select_plan", "dctplus_select",
-    "dctplus_select_factor", "dctplus_select_size", "dctplus_select_destroy",
+    "dctplus_select_factor", "dctplus_select_size", "dctplus_select_destroy", "dctplus_select_tune",
 ]
 
 _ROUTES = {"auto": B.DCTPLUS_ROUTE_AUTO, "fast": B.DCTPLUS_ROUTE_FAST, "dense": B.DCTPLUS_ROUTE_DENSE,
@@ -161,6 +161,20 @@ class SelectPlan:
         B.dctplus_select(self._h, x.data_ptr(), c_p, prune_tau, best.data_ptr(), cost.data_ptr(), y.data_ptr(),
                          _stream(stream))
         return best, cost, y
+
+    def tune(self, x, c_p: int = 0, prune_tau: float = 0.1, stream=None):
+        """Time the persistent grid at 1..4 workgroups per CU on x, keep the fastest for
+        later select() calls; returns (chosen, [ms per call of each candidate])."""
+        import torch
+        if not (x.is_cuda and x.dtype == torch.float32 and x.numel() == self.size):
+            raise ValueError(f"expected a CUDA float32 tensor of {self.size} elements")
+        x = x.contiguous()
+        best = torch.empty(self.n_blocks.shape[0], dtype=torch.int32, device=x.device)
+        cost = torch.empty(self.n_blocks.shape[0], self.K, dtype=torch.float32, device=x.device)
+        y = torch.empty_like(x)
+        _, chosen, ms = B.dctplus_select_tune(self._h, x.data_ptr(), c_p, prune_tau, best.data_ptr(), cost.data_ptr(),
+                                              y.data_ptr(), _stream(stream))
+        return chosen, ms
 
     def factor(self, block: int, r: int):
         return B.dctplus_select_factor(self._h, block, r, int(self.n_blocks[block]))

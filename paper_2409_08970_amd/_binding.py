@@ -29,7 +29,7 @@ EXPORTED = (
     "dctplus_default_opts", "dctplus_plan", "dctplus_forward", "dctplus_adjoint", "dctplus_grad",
     "dctplus_plan_info", "dctplus_plan_table", "dctplus_plan_destroy", "dctplus_status_string",
     "dctplus_last_error", "dctplus_select_plan", "dctplus_select", "dctplus_select_factor",
-    "dctplus_select_size", "dctplus_select_destroy",
+    "dctplus_select_size", "dctplus_select_destroy", "dctplus_select_tune",
 )
 
 
@@ -90,6 +90,9 @@ def load(path: str = LIB_PATH):
     lib.dctplus_select_plan.restype = ctypes.c_int
     lib.dctplus_select.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_double, vp, vp, vp, vp]
     lib.dctplus_select.restype = ctypes.c_int
+    lib.dctplus_select_tune.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_double, vp, vp, vp, vp,
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]
+    lib.dctplus_select_tune.restype = ctypes.c_int
     lib.dctplus_select_factor.argtypes = [vp, i64, ctypes.c_int32, dp]
     lib.dctplus_select_factor.restype = ctypes.c_int
     lib.dctplus_select_size.argtypes = [vp]
@@ -204,6 +207,19 @@ def dctplus_select_plan(n_blocks, K: int, S: int, cand, stream: int = 0, check: 
     if check:
         _check(st, "dctplus_select_plan")
     return st, handle
+
+
+def dctplus_select_tune(plan, x_ptr: int, c_p: int, prune_tau: float, best_ptr: int, cost_ptr: int, y_ptr: int,
+                        stream: int = 0, check: bool = True):
+    """Returns (status, chosen workgroups per CU, [ms per call of each candidate])."""
+    chosen = ctypes.c_int32(0)
+    ms = (ctypes.c_float * 4)()
+    st = load().dctplus_select_tune(plan, ctypes.c_void_p(x_ptr), int(c_p), float(prune_tau), ctypes.c_void_p(best_ptr),
+                                    ctypes.c_void_p(cost_ptr), ctypes.c_void_p(y_ptr), ctypes.c_void_p(stream),
+                                    ctypes.byref(chosen), ms)
+    if check:
+        _check(st, "dctplus_select_tune")
+    return st, chosen.value, list(ms)
 
 
 def dctplus_select(plan, x_ptr: int, c_p: int, prune_tau: float, best_ptr: int, cost_ptr: int, y_ptr: int,

@@ -47,6 +47,7 @@ struct dctplus_select_s {
     int32_t *status_dev = nullptr;
     float *M = nullptr;               // all factors
     float *dctm = nullptr;            // orthonormal DCT-II matrices of the five sizes (factor layout)
+    int32_t wgs_per_cu = 4;           // persistent workgroups per CU (set by dctplus_select_tune)
 };
 
 namespace dctplus {
@@ -54,6 +55,7 @@ namespace dctplus {
 namespace {
 
 constexpr int kSelThreads = 256;
+constexpr int kSelTuneCands = 4;      // persistent grid candidates: 1..4 workgroups per CU
 constexpr int kSelMaxN = 64;
 constexpr int kSelMaxS = 64;
 constexpr int kSelMaxK = 16;
@@ -652,7 +654,7 @@ dctplus_status dctplus_select(dctplus_select_t p, const float *x, int32_t c_p, d
     int ncu = 0;
     hipError_t e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device);
     if (e != hipSuccess || ncu <= 0) ncu = 256;
-    int64_t grid = (int64_t)ncu * 4;       // four 256-thread workgroups per CU (LDS-limited)
+    int64_t grid = (int64_t)ncu * p->wgs_per_cu;   // persistent workgroups (at most 4 per CU fit in LDS)
     if (grid > p->nblocks) grid = p->nblocks;
     SelArgs A;
     A.x = x;
@@ -675,6 +677,53 @@ dctplus_status dctplus_select(dctplus_select_t p, const float *x, int32_t c_p, d
     hipLaunchKernelGGL(k_select, dim3((unsigned)grid), dim3(kSelThreads), 0, s, A);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "selection launch");
     return DCTPLUS_OK;
+}
+
+dctplus_status dctplus_select_tune(dctplus_select_t p, const float *x, int32_t c_p, double prune_tau, int32_t *best,
+                                   float *cost, float *y_best, void *stream, int32_t *chosen, float *ms) {
+    if (!p) return fail(DCTPLUS_EINVAL, "null selection plan");
+    if (p->nblocks == 0) {
+        if (chosen) *chosen = p->wgs_per_cu;
+        return DCTPLUS_OK;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    const int32_t keep = p->wgs_per_cu;
+    float best_ms = 0.0f;
+    int32_t best_c = keep;
+    dctplus_status st = DCTPLUS_OK;
+    for (int32_t c = 1; c <= kSelTuneCands && st == DCTPLUS_OK; ++c) {
+        p->wgs_per_cu = c;
+        st = dctplus_select(p, x, c_p, prune_tau, best, cost, y_best, stream);      // warm-up, validates
+        if (st != DCTPLUS_OK) break;
+        (void)hipEventRecord(e0, s);
+        for (int it = 0; it < 3 && st == DCTPLUS_OK; ++it)
+            st = dctplus_select(p, x, c_p, prune_tau, best, cost, y_best, stream);
+        (void)hipEventRecord(e1, s);
+        if (st != DCTPLUS_OK) break;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+            st = hip_fail(e, "hipEventSynchronize");
+            break;
+        }
+        float t = 0.0f;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        t /= 3.0f;
+        if (ms) ms[c - 1] = t;
+        if (c == 1 || t < best_ms) {
+            best_ms = t;
+            best_c = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->wgs_per_cu = (st == DCTPLUS_OK) ? best_c : keep;
+    if (st == DCTPLUS_OK && chosen) *chosen = best_c;
+    return st;
 }
 
 dctplus_status dctplus_select_factor(dctplus_select_t p, int64_t block, int32_t r, double *dst) {

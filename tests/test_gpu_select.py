@@ -225,3 +225,22 @@ def test_select_empty_plan_and_argument_errors():
     with pytest.raises(ValueError):
         sel.select(torch.zeros(total - 1, device="cuda"))
     sel.close()
+
+
+def test_select_tune_picks_a_grid_and_keeps_results():
+    """The launch autotuner times the persistent grid at 1..4 workgroups per CU and
+    keeps the fastest; the result does not depend on the grid (bit-identical)."""
+    torch = _torch()
+    from paper_2409_08970_amd import SelectPlan
+    W = workloads.workload4(blocks=400, sub=4)
+    sel = SelectPlan(W["n"], W["cand"], S=W["signals"])
+    x = torch.from_numpy(np.ascontiguousarray(W["x"], dtype=np.float32)).cuda()
+    ref = [t.clone() for t in sel.select(x)]
+    chosen, ms = sel.tune(x)
+    assert chosen in (1, 2, 3, 4) and len(ms) == 4 and all(t > 0 for t in ms)
+    assert ms[chosen - 1] == min(ms)
+    out = sel.select(x)
+    torch.cuda.synchronize()
+    for a, b in zip(ref, out):
+        assert torch.equal(a, b)
+    sel.close()
