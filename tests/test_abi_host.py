@@ -106,6 +106,12 @@ def test_calls_on_null_plan_are_rejected(lib):
     assert lib.dctplus_grad(None, None, None, 4, None, None, None, None) == 1
     assert lib.dctplus_plan_info(None, None, None, None, None, None) == 1
     lib.dctplus_plan_destroy(None)
+    from paper_2409_08970_amd import _binding as B
+    B.load()
+    assert lib.dctplus_select(None, None, 0, 0.1, None, None, None, None) == 1
+    assert lib.dctplus_select_tune(None, None, 0, 0.1, None, None, None, None, None, None) == 1
+    assert lib.dctplus_select_size(None) == -1
+    lib.dctplus_select_destroy(None)
 
 
 @pytest.mark.parametrize("nb,K,S,cand_row,expect", [

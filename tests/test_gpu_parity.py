@@ -145,7 +145,7 @@ def test_forward_and_adjoint_parity(route, n, kind):
 
 
 @pytest.mark.parametrize("route", ["fast", "dense"])
-@pytest.mark.parametrize("n", [1024, 4096, 16384])
+@pytest.mark.parametrize("n", [1024, 2048, 4096, 8192, 16384])
 @pytest.mark.parametrize("kind", ["dense", "edge"])
 def test_large_n_full_batch_sampled(route, n, kind):
     """Workload-3 shape (256 N(0,1) signals): the whole batch runs on the GPU,
