@@ -432,13 +432,10 @@ FastCfg fast_config(const dctplus_plan_s *p) {
     c.threads = n <= 256 ? 256 : 1024;
     const size_t per_big = sizeof(double) * big_doubles(n);
     const size_t per_small = tdsz * n + sizeof(double) * (nd + 1);
-    static int lds_max = 0;
-    if (lds_max == 0) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) != hipSuccess || v <= 0)
-            v = 64 * 1024;
-        lds_max = v;
-    }
+    int lds_max = 0;   // per device (a host-side query)
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) != hipSuccess ||
+        lds_max <= 0)
+        lds_max = 64 * 1024;
     size_t budget = (size_t)lds_max - 4096;
     if (budget > 150 * 1024) budget = 150 * 1024;
     c.big_in_lds = (per_big + per_small) <= budget;
