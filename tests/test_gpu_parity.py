@@ -268,6 +268,26 @@ def test_fp64_fast_parity(n, batch, kind):
     assert relerr(xa, oracle.semi_adjoint(n, rho, v, yin, sp)) <= TOL_FAST64, (n, kind)
 
 
+@pytest.mark.parametrize("n", [16, 64, 256])
+def test_fast_route_exact_row_threshold(n):
+    """direct_kappa bounds the NUFFT error amplification a row may have before it is
+    summed exactly.  At 1e-9 every row of these plans is exact, and the FAST route
+    then reproduces the Cauchy product to FP64 rounding; a threshold that would need
+    more exact rows than the kernels hold is refused at plan time."""
+    _torch()
+    from paper_2409_08970_amd import Plan, _binding as B
+    rho, v = case(n, "dense")
+    x = np.random.default_rng(n).standard_normal((40, n))
+    p = make_plan(n, rho, v, "fast", dtype="f64", direct_kappa=1e-9)
+    assert int(p.info["counts"][1]) == n               # every row exact (no deflation here)
+    y = run(p, x)
+    p.close()
+    sp = oracle.semi_plan(n, rho, v)
+    assert relerr(y, oracle.semi_forward(n, rho, v, x, sp)) <= TOL64
+    with pytest.raises(B.DctPlusError):
+        Plan(4096, rho, workloads.unit_vector(np.random.default_rng(1), 4096), route="fast", direct_kappa=1e-9)
+
+
 @pytest.mark.parametrize("route", ["dense", "gft"])
 @pytest.mark.parametrize("n", [4, 8, 16, 32, 64, 128, 256, 1024])
 @pytest.mark.parametrize("kind", ["dense", "loopn", "edge", "negative"])
