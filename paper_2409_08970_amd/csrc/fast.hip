@@ -271,13 +271,18 @@ __global__ void __launch_bounds__(1024) k_fast_adj(PlanTables t, const TIO *__re
         const int r = (b < n - 1) ? t.rowOfBin[b] : -1;
         yb[g] = (r >= 0) ? (TD)y[(s0 + s) * n + r] : (TD)0;
     }
+    double *ydir = sd0 + nsig;   // [ns * nd] input values of the exact rows
+    for (int g = tid; g < ns * nd; g += nthr) {
+        const int s = g / nd, r = g % nd;
+        ydir[g] = (double)(TD)y[(s0 + s) * n + t.direct_row[r]];
+    }
     __syncthreads();
 
     // transpose of the s_0 / mu compensation: sd0 = sum_b rowB_b y_row(b); each signal's
     // sum is split over wps waves, the partial sums added in a fixed order
     const int wave = tid >> 6, lane = tid & 63, nwave = nthr >> 6;
     const int wps = ns < nwave ? nwave / ns : 1;
-    double *part = sd0 + nsig;   // [ns * wps <= nwave] partial sums
+    double *part = ydir + (size_t)nsig * nd;   // [ns * wps <= nwave] partial sums
     for (int it = wave; it < ns * wps; it += nwave) {
         const int s = it / wps, c = it % wps;
         double acc = 0.0;
@@ -398,10 +403,10 @@ __global__ void __launch_bounds__(1024) k_fast_adj(PlanTables t, const TIO *__re
     for (int g = tid; g < ns * n; g += nthr) {
         const int s = g / n, j = g % n;
         double v = (j == 0) ? sd0[s] : t.hz[j] * dst1_post(Bc + (size_t)s * strideB, j, logn, rpB, t.tw64, logT);
-        const TIO *ys = y + (s0 + s) * n;   // deflated and exact rows come straight from the input
+        const TIO *ys = y + (s0 + s) * n;   // deflated rows come straight from the input
         const int rk = t.rowOfK[j];
         if (rk >= 0) v += (double)(TD)ys[rk];
-        for (int r = 0; r < nd; ++r) v += t.direct[(size_t)r * n + j] * (double)(TD)ys[t.direct_row[r]];
+        for (int r = 0; r < nd; ++r) v += t.direct[(size_t)r * n + j] * ydir[(size_t)s * nd + r];
         big[(size_t)s * BD + 2 * n + j] = v;
     }
     __syncthreads();
