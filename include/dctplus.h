@@ -55,7 +55,8 @@ typedef enum {
     DCTPLUS_ENOMEM = 2,       /* device or host allocation failed */
     DCTPLUS_EDEVICE = 3,      /* HIP runtime error (see dctplus_last_error) */
     DCTPLUS_EUNSUPPORTED = 4, /* valid request outside what this build implements (route, dtype, n) */
-    DCTPLUS_ENOCONV = 5       /* the secular-equation solver did not converge */
+    DCTPLUS_ENOCONV = 5,      /* the secular-equation solver did not converge */
+    DCTPLUS_EDEGENERATE = 6   /* the request needs simple eigenvalues and the plan has a double one */
 } dctplus_status;
 
 /* Element type of signals, and the arithmetic of the bulk of the transform. */
@@ -132,6 +133,12 @@ dctplus_status dctplus_adjoint(dctplus_plan_t plan, const void *y, void *x, int6
  * w = X^T v:  dl/drho = w^T A w,  dl/dv = rho X (A + A^T) w  (first-order
  * eigenvector perturbation of L x_i = mu_i x_i, with Lemma 4.2 for w).
  * Uses the plan's workspace: calls on one plan must not overlap.
+ * Errors (all detected before any device work, so nothing is written):
+ *   EUNSUPPORTED  grho or gv requested with n > 4096;
+ *   EDEGENERATE   grho or gv requested on a plan with a double eigenvalue (a secular
+ *                 root on a deflated lambda_k, e.g. a mirror-symmetric added edge): the
+ *                 eigenbasis, and the row order, are not differentiable in (rho, v)
+ *                 there.  dl/dx alone is always available.
  */
 dctplus_status dctplus_grad(dctplus_plan_t plan, const void *y, const void *gy, int64_t batch, void *gx,
                             double *grho, double *gv, void *stream);
@@ -148,8 +155,8 @@ dctplus_status dctplus_plan_info(dctplus_plan_t plan, double *mu, double *a, dou
 
 /* Copy one named plan table to HOST memory (synchronous; for tests and tools).
  * name: "z", "zraw", "mu", "a", "tau", "hz", "deconv", "rowA", "rowB", "win", "direct",
- *       "sintab" (double); "origin", "kind", "ref", "m0", "rowOfBin", "rowOfK", "direct_row"
- *       (int32).  *bytes: capacity of dst on input, size of the table on output;
+ *       "sintab" (double); "origin", "kind", "ref", "m0", "rowOfBin", "rowOfK", "direct_row",
+ *       "ntie" (one value: the number of secular roots tying a deflated lambda) (int32).  *bytes: capacity of dst on input, size of the table on output;
  *       dst may be NULL to query the size.  Unknown name: EINVAL. */
 dctplus_status dctplus_plan_table(dctplus_plan_t plan, const char *name, void *dst, int64_t *bytes);
 

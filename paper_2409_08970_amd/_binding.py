@@ -21,6 +21,7 @@ DCTPLUS_ENOMEM = 2
 DCTPLUS_EDEVICE = 3
 DCTPLUS_EUNSUPPORTED = 4
 DCTPLUS_ENOCONV = 5
+DCTPLUS_EDEGENERATE = 6
 
 DCTPLUS_F32, DCTPLUS_F64, DCTPLUS_BF16, DCTPLUS_F32_SPLIT = 0, 1, 2, 3
 DCTPLUS_ROUTE_AUTO, DCTPLUS_ROUTE_FAST, DCTPLUS_ROUTE_DENSE, DCTPLUS_ROUTE_GFT = 0, 1, 2, 3
@@ -172,7 +173,7 @@ def dctplus_plan_info(plan, n: int):
     return dict(mu=mu, a=a, z=z, kind=kind, counts=counts)
 
 
-_INT_TABLES = {"origin", "kind", "ref", "m0", "rowOfBin", "rowOfK", "direct_row"}
+_INT_TABLES = {"origin", "kind", "ref", "m0", "rowOfBin", "rowOfK", "direct_row", "ntie"}
 
 
 def dctplus_plan_table(plan, name: str):

@@ -234,6 +234,7 @@ dctplus_status dctplus_plan_table(dctplus_plan_t p, const char *name, void *dst,
         {"origin", p->t.origin, 4 * n}, {"kind", p->t.kind, 4 * n}, {"ref", p->t.ref, 4 * n},
         {"m0", p->t.m0, 4 * n}, {"rowOfBin", p->t.rowOfBin, 4 * n}, {"rowOfK", p->t.rowOfK, 4 * n},
         {"direct_row", p->t.direct_row, 4 * (nd < kMaxDirect ? nd : kMaxDirect)},
+        {"ntie", p->t.status + 4, 4},
     };
     for (const Entry &e : tab) {
         if (strcmp(e.name, name) != 0) continue;
@@ -275,6 +276,7 @@ const char *dctplus_status_string(dctplus_status s) {
         case DCTPLUS_EDEVICE: return "device error";
         case DCTPLUS_EUNSUPPORTED: return "unsupported";
         case DCTPLUS_ENOCONV: return "secular solver did not converge";
+        case DCTPLUS_EDEGENERATE: return "double eigenvalue";
     }
     return "unknown status";
 }

@@ -56,6 +56,7 @@ struct PlanTables {
     double *mt64;       // [n * n] FP64 X^T (FP64 plans)
     int32_t *status;    // [4]    plan-build status words
     int ndirect, ndefl, width, nj;
+    int ntie;           // secular roots tying a deflated lambda_k (double eigenvalues)
     int folded;         // dense factor holds X^T (DCT folded in) rather than M
 };
 

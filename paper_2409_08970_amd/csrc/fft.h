@@ -280,6 +280,20 @@ __device__ __forceinline__ T dst1_post(const cplx<T> *Zh, int l, int logNn, cons
 }
 
 // ---------------------------------------------------------------------------
+// Eigenvalue gaps of the path graph in product form
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double sin_half(const double *sintab, int n, int k) {
+    // sin(pi k / 2n) for -2n <= k <= 2n, from the table sintab[k] = sin(pi k / 2n), k = 0..2n
+    return k >= 0 ? sintab[k] : -sintab[-k];
+}
+
+// lambda_j - lambda_o = 4 sin(pi (j - o) / 2n) sin(pi (j + o) / 2n): no cancellation, so
+// small gaps keep full relative accuracy
+__device__ __forceinline__ double lam_diff(const double *sintab, int n, int j, int o) {
+    return 4.0 * sin_half(sintab, n, j - o) * sin_half(sintab, n, j + o);
+}
+
+// ---------------------------------------------------------------------------
 // Reductions
 // ---------------------------------------------------------------------------
 template <typename T>

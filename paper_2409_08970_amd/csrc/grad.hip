@@ -117,7 +117,9 @@ __global__ void __launch_bounds__(256) k_gram_sum(const float *__restrict__ part
 }
 
 // r_i = sum_k (G_ik - G_ki) / (mu_i - mu_k) w_k ,  q_i = w_i sum_k G_ik w_k / (mu_i - mu_k);
-// one wave per i, lanes over k.
+// one wave per i, lanes over k.  Every eigenvalue is stored as its origin pole and offset,
+// mu = lambda_o + tau, so the gap is (lambda_oi - lambda_ok) + (tau_i - tau_k) with the pole
+// difference in product form: a root hugging a pole keeps the gap's relative accuracy.
 __global__ void __launch_bounds__(256) k_grad_vec(PlanTables t, const double *__restrict__ G,
                                                   const double *__restrict__ GT, double *__restrict__ rvec,
                                                   double *__restrict__ qvec) {
@@ -125,12 +127,13 @@ __global__ void __launch_bounds__(256) k_grad_vec(PlanTables t, const double *__
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (i >= n) return;   // the whole wave leaves
-    const double mui = t.mu[i];
+    const int oi = t.origin[i];
+    const double taui = t.tau[i];
     double r = 0.0, q = 0.0;
     for (int k = lane; k < n; k += 64) {
         if (k == i) continue;
         const double gik = G[(size_t)i * n + k], gki = GT[(size_t)i * n + k];
-        const double inv = 1.0 / (mui - t.mu[k]);
+        const double inv = 1.0 / (lam_diff(t.sintab, n, oi, t.origin[k]) + (taui - t.tau[k]));
         const double wk = wcoef(t, k);
         r += (gik - gki) * inv * wk;
         q += gik * inv * wk;
@@ -205,13 +208,20 @@ __global__ void __launch_bounds__(256) k_grad_final(PlanTables t, const double *
 dctplus_status grad_apply(dctplus_plan_s *p, const float *y, const float *gy, int64_t batch, float *gx,
                           double *grho, double *gv, hipStream_t s) {
     const int n = (int)p->n;
+    // every refusal comes before the first launch: no output is written on error
+    if ((grho || gv) && n > 4096)
+        return fail(DCTPLUS_EUNSUPPORTED, "gradient with respect to rho and v supports n <= 4096");
+    // a double eigenvalue (a secular root on a deflated lambda_k) has no unique eigenbasis:
+    // the basis, and the row order, are not differentiable in (rho, v) there
+    if ((grho || gv) && p->t.ntie > 0)
+        return fail(DCTPLUS_EDEGENERATE, "the plan has %d double eigenvalue(s): d/drho and d/dv are undefined",
+                    p->t.ntie);
     if (gx) {
         dctplus_status st = (p->route == DCTPLUS_ROUTE_FAST) ? fast_apply(p, gy, gx, batch, true, s)
                                                              : dense_apply(p, gy, gx, batch, true, s);
         if (st != DCTPLUS_OK) return st;
     }
     if (!grho && !gv) return DCTPLUS_OK;
-    if (n > 4096) return fail(DCTPLUS_EUNSUPPORTED, "gradient with respect to rho and v supports n <= 4096");
     // split-K so that the grid has ~512+ workgroups and the partials stay modest
     const int nt = (n + GT - 1) / GT;
     const int tiles = nt * nt;

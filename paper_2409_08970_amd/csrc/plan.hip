@@ -29,16 +29,6 @@ namespace {
 constexpr int kPlanThreads = 1024;
 constexpr int kQuad = 192;  // Gauss-Legendre nodes for the window transform
 
-__device__ __forceinline__ double sin_half(const double *sintab, int n, int k) {
-    // sin(pi k / 2n) for -2n <= k <= 2n
-    return k >= 0 ? sintab[k] : -sintab[-k];
-}
-
-__device__ __forceinline__ double lam_diff(const double *sintab, int n, int j, int o) {
-    // lambda_j - lambda_o
-    return 4.0 * sin_half(sintab, n, j - o) * sin_half(sintab, n, j + o);
-}
-
 __device__ __forceinline__ double lam(const double *sintab, int n, int k) {
     const double s = sintab[k];
     return 4.0 * s * s;
@@ -301,9 +291,11 @@ __global__ void __launch_bounds__(kPlanThreads) k_rows(PlanTables t, const int32
         t.a[row] = r_a[r];
         t.origin[row] = o;
         t.tau[row] = tau;
-        // bin between lambda_b and lambda_{b+1}
-        const int b = (tau > 0.0) ? o : o - 1;
-        bool direct = (b < 0 || b > n - 2 || !(mu > 0.0) || !(mu < 4.0));
+        // a root tying a deflated lambda_k (a double eigenvalue): lo is the largest k with
+        // lambda_k <= mu + tie, and the gap is formed in offset form
+        if (lo >= 0 && t.z[lo] == 0.0 && fabs(lam_diff(t.sintab, n, lo, o) - tau) <= tie)
+            atomicAdd(&t.status[4], 1);
+        bool direct = !(mu > 0.0) || !(mu < 4.0);
         if (!direct) {
             const double th = M_PI * o / n;
             double d;
@@ -319,24 +311,28 @@ __global__ void __launch_bounds__(kPlanThreads) k_rows(PlanTables t, const int32
             const double sn = ((o & 1) ? -1.0 : 1.0) * sin(n * d);
             const double a = r_a[r];
             const double kappa = (sn != 0.0) ? a * sqrt(2.0 * n) * maxhz / (2.0 * fabs(sn)) : INFINITY;
-            if (!(kappa <= kappa_max)) {
-                direct = true;
-            } else {
-                const double psi = th + d;
-                const double x = psi / hgrid;
-                const int m0 = (int)ceil(x - 0.5 * w);
+            const double psi = th + d;
+            const double x = psi / hgrid;
+            // the Chebyshev bin (theta_b, theta_b+1) the root lies in, from its angle: a
+            // deflated lambda between the root and its origin puts it past the origin's bin
+            const int b = (int)floor(0.5 * x);
+            const int m0 = (int)ceil(x - 0.5 * w);
+            // the aligned taps start at 2b + 1 - w/2: the first real tap must sit 0..2 past it
+            const int sh = m0 - (2 * b + 1 - w / 2);
+            direct = !(kappa <= kappa_max) || b < 0 || b > n - 2 || sh < 0 || sh > 2;
+            // interlacing leaves at most one root per bin; a root on a bin boundary (rounding)
+            // that finds its bin taken is summed exactly instead
+            if (!direct) direct = atomicCAS(&rowOfBin[b], -1, row) != -1;
+            if (!direct) {
                 t.rowA[b] = -0.5 * a / sn;
                 t.rowB[b] = a * t.z[0] / mu;
                 t.m0[b] = m0;
                 for (int q = 0; q < w; ++q) t.win[(size_t)b * w + q] = es_window(x - (m0 + q), w, beta);
-                // the same taps on the aligned origin 2b + 1 - w/2 (m0 is that origin or the next point)
-                const int sh = m0 - (2 * b + 1 - w / 2);
                 for (int k = 0; k < w + 2; ++k) {
                     const int q = k - sh;
                     t.wina[(size_t)b * kTaps + k] =
                         (q >= 0 && q < w) ? t.rowA[b] * es_window(x - (m0 + q), w, beta) : 0.0;
                 }
-                rowOfBin[b] = row;
                 t.kind[row] = ROW_NUFFT;
                 t.ref[row] = b;
             }
@@ -508,6 +504,7 @@ dctplus_status plan_build(dctplus_plan_s *p, const double *v_host, hipStream_t s
     t.nj = st[1];
     t.ndefl = st[2];
     t.ndirect = st[3];
+    t.ntie = st[4];
     const bool need_fast = (p->route == DCTPLUS_ROUTE_FAST);
     if (need_fast && t.ndirect > kMaxDirect)
         return fail(DCTPLUS_EUNSUPPORTED, "%d ill-conditioned rows exceed the FAST route limit %d", t.ndirect,

@@ -389,6 +389,44 @@ def test_select_block_pruning_limits():
     assert np.all(np.linalg.norm(yf - y2, axis=1) <= bound + 1e-12)
 
 
+def graph_laplacian(n, edges=(), loops=()):
+    """Generalized Laplacian D - W + V of a weighted graph (Def. of the GFT):
+    W the weighted adjacency (unit path edges (j, j+1) plus the extra edges,
+    whose weights add to an existing edge), D its degree matrix, V the diagonal
+    self-loop matrix.  Built from the graph alone, not from a rank-one term."""
+    W = np.zeros((n, n))
+    for j in range(n - 1):
+        W[j, j + 1] = W[j + 1, j] = 1.0
+    for (i, j, w) in edges:
+        W[i, j] += w
+        W[j, i] += w
+    V = np.zeros((n, n))
+    for (i, w) in loops:
+        V[i, i] += w
+    return np.diag(W.sum(axis=1)) - W + V
+
+
+def pin_candidate_update(update_fn, n):
+    """Largest gap between L_path + rho v v^T, with (rho, v) from update_fn, and the
+    generalized Laplacian of the graph the candidate describes (a self-loop of
+    weight w at i, or an edge of weight w between i and j: Prop. on baby Laplacians,
+    scenarios (i) and (ii))."""
+    worst = 0.0
+    cases = [(0, 0, 0, 0.7), (0, n - 1, n - 1, 1.9), (1, 1, n - 2, 1.0), (1, 0, 1, 0.35),
+             (1, n // 2 - 1, n // 2, 2.5), (1, 2, n - 1, 0.6)]
+    for (kind, i, j, w) in cases:
+        rho, v = update_fn(n, kind, i, j, w)
+        L = oracle.laplacian(n, rho, v)
+        G = graph_laplacian(n, loops=[(i, w)]) if kind == 0 else graph_laplacian(n, edges=[(i, j, w)])
+        worst = max(worst, np.abs(L - G).max())
+    return worst
+
+
+@pytest.mark.parametrize("n", [4, 8, 16, 64])
+def test_candidate_update_is_the_graph_laplacian(n):
+    assert pin_candidate_update(oracle.candidate_update, n) < 1e-14
+
+
 # --------------------------------------------------------------------------
 # mutation tests: plausible mistakes must trip at least one pin
 # --------------------------------------------------------------------------
@@ -421,6 +459,21 @@ def _lap_rho_twice(n, rho, v):
 
 def _signs_flipped(X, rho, v):
     return -oracle.fix_signs(X, rho, v)
+
+
+def _update_edge_rho_w(n, kind, i, j, w):
+    rho, v = oracle.candidate_update(n, kind, i, j, w)
+    return (w, v) if kind == 1 else (rho, v)       # edge weight w read as rho = w
+
+
+def _update_loop_unit_v_scaled(n, kind, i, j, w):
+    rho, v = oracle.candidate_update(n, kind, i, j, w)
+    return (rho, v / np.sqrt(2.0)) if kind == 0 else (rho, v)
+
+
+@pytest.mark.parametrize("mutant", [_update_edge_rho_w, _update_loop_unit_v_scaled])
+def test_candidate_update_pin_catches_mutants(mutant):
+    assert pin_candidate_update(mutant, 16) > 0.1
 
 
 @pytest.mark.parametrize("mutant", ["offdiag", "end_degree", "rho_twice", "signs", "order"])
