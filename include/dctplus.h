@@ -144,6 +144,28 @@ dctplus_status dctplus_grad(dctplus_plan_t plan, const void *y, const void *gy, 
                             double *grho, double *gv, void *stream);
 
 /*
+ * dctplus_grad without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as dctplus_grad; the
+ * Gram partials, G and the O(n) vectors live in one fixed 16 MiB device
+ * array per GPU, set up on the first call on that GPU and held until the
+ * process ends.  Nothing of the array needs to start at zero (every kernel
+ * writes the whole of what it later reads).  No hipMalloc, hipFree or
+ * allocating library routine is called.
+ * Limits (EUNSUPPORTED, before any device work):
+ *   - grho or gv requested with n > 512 (the scratch holds the n x n G and G^T
+ *     in FP64 plus at least one n x n FP32 partial);
+ *   - gx requested on a plan whose adjoint needs the plan workspace or the GEMM
+ *     library: FP32 DENSE/GFT plans with n > 64, and FAST plans whose per-signal
+ *     buffer does not fit in LDS.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (different streams, threads or plans) race and give wrong results;
+ * order them (one stream, or events).
+ */
+dctplus_status dctplus_grad_noalloc(dctplus_plan_t plan, const void *y, const void *gy, int64_t batch, void *gx,
+                                    double *grho, double *gv, void *stream);
+
+/*
  * Copy plan tables to HOST arrays (synchronous; for tests and tools).
  * Any pointer may be NULL.  mu, a: n doubles in row order (a_i = 1 for
  * deflated rows); z: n doubles, U^T v after deflation; kind: n int32 per row

@@ -19,13 +19,14 @@ import ctypes
 
 from . import _binding as B
 from ._binding import (DctPlusError, dctplus_adjoint, dctplus_default_opts, dctplus_forward, dctplus_grad,
+                       dctplus_grad_noalloc,
                        dctplus_last_error, dctplus_plan, dctplus_plan_destroy, dctplus_plan_info,
                        dctplus_plan_table, dctplus_select, dctplus_select_destroy, dctplus_select_factor,
                        dctplus_select_plan, dctplus_select_size, dctplus_select_tune, dctplus_status_string)
 
 __all__ = [
     "Plan", "DctPlusFn", "dctplus", "DctPlusError", "dctplus_plan", "dctplus_forward", "dctplus_adjoint",
-    "dctplus_grad", "dctplus_plan_info", "dctplus_plan_table", "dctplus_plan_destroy", "dctplus_status_string",
+    "dctplus_grad", "dctplus_grad_noalloc", "dctplus_plan_info", "dctplus_plan_table", "dctplus_plan_destroy", "dctplus_status_string",
     "dctplus_last_error", "dctplus_default_opts", "SelectPlan", "dctplus_select_plan", "dctplus_select",
     "dctplus_select_factor", "dctplus_select_size", "dctplus_select_destroy", "dctplus_select_tune",
 ]

@@ -30,7 +30,7 @@ EXPORTED = (
     "dctplus_default_opts", "dctplus_plan", "dctplus_forward", "dctplus_adjoint", "dctplus_grad",
     "dctplus_plan_info", "dctplus_plan_table", "dctplus_plan_destroy", "dctplus_status_string",
     "dctplus_last_error", "dctplus_select_plan", "dctplus_select", "dctplus_select_factor",
-    "dctplus_select_size", "dctplus_select_destroy", "dctplus_select_tune",
+    "dctplus_select_size", "dctplus_select_destroy", "dctplus_select_tune", "dctplus_grad_noalloc",
 )
 
 
@@ -77,6 +77,8 @@ def load(path: str = LIB_PATH):
     lib.dctplus_adjoint.restype = ctypes.c_int
     lib.dctplus_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
     lib.dctplus_grad.restype = ctypes.c_int
+    lib.dctplus_grad_noalloc.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
+    lib.dctplus_grad_noalloc.restype = ctypes.c_int
     lib.dctplus_plan_info.argtypes = [vp, dp, dp, dp, i32p, i32p]
     lib.dctplus_plan_info.restype = ctypes.c_int
     lib.dctplus_plan_table.argtypes = [vp, ctypes.c_char_p, vp, ctypes.POINTER(ctypes.c_int64)]
@@ -154,6 +156,16 @@ def dctplus_grad(plan, y_ptr: int, gy_ptr: int, batch: int, gx_ptr: int, grho_pt
                              ctypes.c_void_p(gv_ptr or None), ctypes.c_void_p(stream))
     if check:
         _check(st, "dctplus_grad")
+    return st
+
+
+def dctplus_grad_noalloc(plan, y_ptr: int, gy_ptr: int, batch: int, gx_ptr: int, grho_ptr: int, gv_ptr: int,
+                         stream: int = 0, check: bool = True) -> int:
+    st = load().dctplus_grad_noalloc(plan, ctypes.c_void_p(y_ptr), ctypes.c_void_p(gy_ptr), int(batch),
+                                     ctypes.c_void_p(gx_ptr or None), ctypes.c_void_p(grho_ptr or None),
+                                     ctypes.c_void_p(gv_ptr or None), ctypes.c_void_p(stream))
+    if check:
+        _check(st, "dctplus_grad_noalloc")
     return st
 
 

@@ -5,9 +5,16 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "common.h"
+
+// Scratch of dctplus_grad_noalloc: one fixed device array per GPU, held until
+// the process ends.  Host code never uses its name as an address: the device
+// address of each GPU's copy is looked up once per device (scratch_ptr).
+constexpr size_t kStaticScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 namespace dctplus {
 
@@ -43,6 +50,37 @@ dctplus_status ensure_work(dctplus_plan_s *p, size_t bytes) {
     }
     p->work_bytes = bytes;
     return DCTPLUS_OK;
+}
+
+// Device address of this GPU's copy of `scratch`, looked up on the first call
+// with that device current.
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+static dctplus_status scratch_ptr(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(DCTPLUS_EUNSUPPORTED, "device %d: at most %d devices", dev,
+                                                   kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return e != hipSuccess ? hip_fail(e, "hipGetSymbolAddress(scratch)")
+                                   : fail(DCTPLUS_EDEVICE, "no device address for the static scratch");
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return DCTPLUS_OK;
+}
+
+bool route_alloc_free(const dctplus_plan_s *p) {
+    if (p->route == DCTPLUS_ROUTE_FAST) return fast_in_lds(p);
+    // dense routes: FP64 and n <= 64 run our kernels without workspace; FP32 above
+    // n = 64 calls the GEMM library (and the factored form a DCT pass in the workspace)
+    return p->dtype == DCTPLUS_F64 || p->n <= 64;
 }
 
 static bool aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
@@ -198,6 +236,28 @@ dctplus_status dctplus_grad(dctplus_plan_t p, const void *y, const void *gy, int
     dctplus_status st = set_device(p);
     if (st != DCTPLUS_OK) return st;
     return grad_apply(p, (const float *)y, (const float *)gy, batch, (float *)gx, grho, gv, (hipStream_t)stream);
+}
+
+dctplus_status dctplus_grad_noalloc(dctplus_plan_t p, const void *y, const void *gy, int64_t batch, void *gx,
+                                    double *grho, double *gv, void *stream) {
+    if (!p) return fail(DCTPLUS_EINVAL, "null plan");
+    if (p->dtype != DCTPLUS_F32 && p->dtype != DCTPLUS_F32_SPLIT)
+        return fail(DCTPLUS_EUNSUPPORTED, "gradients are implemented for FP32 plans");
+    if (batch < 0) return fail(DCTPLUS_EINVAL, "batch = %lld < 0", (long long)batch);
+    if (!y || !gy) return fail(DCTPLUS_EINVAL, "null y or gy");
+    if (!aligned(y, 4) || !aligned(gy, 4) || (gx && !aligned(gx, 4)) || (grho && !aligned(grho, 8)) ||
+        (gv && !aligned(gv, 8)))
+        return fail(DCTPLUS_EINVAL, "misaligned pointer");
+    if (gx) {
+        dctplus_status st = check_io(p, gy, gx, batch);
+        if (st != DCTPLUS_OK) return st;
+    }
+    dctplus_status st = set_device(p);
+    if (st != DCTPLUS_OK) return st;
+    void *ptr = nullptr;
+    if ((st = scratch_ptr(p->device, &ptr)) != DCTPLUS_OK) return st;
+    return grad_apply_static(p, (const float *)y, (const float *)gy, batch, (float *)gx, grho, gv, ptr,
+                             kStaticScratchBytes, (hipStream_t)stream);
 }
 
 dctplus_status dctplus_plan_info(dctplus_plan_t p, double *mu, double *a, double *z, int32_t *kind,

@@ -94,6 +94,13 @@ dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s);
 void dense_release(dctplus_plan_s *p);
 dctplus_status grad_apply(dctplus_plan_s *p, const float *y, const float *gy, int64_t batch, float *gx,
                           double *grho, double *gv, hipStream_t s);
+// the gradient with its scratch in a caller-given device buffer (no allocation)
+constexpr int kStaticGradMaxN = 512;
+dctplus_status grad_apply_static(dctplus_plan_s *p, const float *y, const float *gy, int64_t batch, float *gx,
+                                 double *grho, double *gv, void *scratch, size_t scratch_bytes, hipStream_t s);
+// true when the plan's forward and adjoint need neither the plan workspace nor a library call
+bool route_alloc_free(const dctplus_plan_s *p);
+bool fast_in_lds(const dctplus_plan_s *p);
 dctplus_status plan_build(dctplus_plan_s *p, const double *v_host, hipStream_t s);
 dctplus_status ensure_work(dctplus_plan_s *p, size_t bytes);
 }  // namespace dctplus

@@ -467,6 +467,8 @@ void launch_fast(dctplus_plan_s *p, const FastCfg &c, dim3 grid, dim3 block, con
 
 }  // namespace
 
+bool fast_in_lds(const dctplus_plan_s *p) { return fast_config(p).big_in_lds; }
+
 dctplus_status fast_apply(dctplus_plan_s *p, const void *in, void *out, int64_t batch, bool adjoint,
                           hipStream_t s) {
     const FastCfg c = fast_config(p);

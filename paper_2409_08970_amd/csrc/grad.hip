@@ -203,44 +203,47 @@ __global__ void __launch_bounds__(256) k_grad_final(PlanTables t, const double *
     for (int j = tid; j < n; j += nthr) gv[j] = t.rho * dct3_sample(Z, j, logn, rp);
 }
 
-}  // namespace
+// Gram split count: ~512+ workgroups over the 128 x 128 output tiles, partials within
+// `cap` bytes (the workspace), at least one split.
+static int gram_splits(int n, size_t cap) {
+    const int nt = (n + GT - 1) / GT;
+    const int tiles = nt * nt;
+    int nsplit = 512 / tiles;
+    if (nsplit < 1) nsplit = 1;
+    if (nsplit > 128) nsplit = 128;
+    while (nsplit > 1 && (size_t)nsplit * n * n * sizeof(float) > cap) nsplit >>= 1;
+    return nsplit;
+}
 
-dctplus_status grad_apply(dctplus_plan_s *p, const float *y, const float *gy, int64_t batch, float *gx,
-                          double *grho, double *gv, hipStream_t s) {
-    const int n = (int)p->n;
-    // every refusal comes before the first launch: no output is written on error
-    if ((grho || gv) && n > 4096)
+static size_t grad_tail_bytes(int n) {
+    return 2 * sizeof(double) * (size_t)n * n + 3 * sizeof(double) * n;   // G, G^T, r, q, s
+}
+
+// Checks shared by both gradient entry points (before any launch: no output on error).
+static dctplus_status grad_check(const dctplus_plan_s *p, const double *grho, const double *gv) {
+    if ((grho || gv) && p->n > 4096)
         return fail(DCTPLUS_EUNSUPPORTED, "gradient with respect to rho and v supports n <= 4096");
     // a double eigenvalue (a secular root on a deflated lambda_k) has no unique eigenbasis:
     // the basis, and the row order, are not differentiable in (rho, v) there
     if ((grho || gv) && p->t.ntie > 0)
         return fail(DCTPLUS_EDEGENERATE, "the plan has %d double eigenvalue(s): d/drho and d/dv are undefined",
                     p->t.ntie);
-    if (gx) {
-        dctplus_status st = (p->route == DCTPLUS_ROUTE_FAST) ? fast_apply(p, gy, gx, batch, true, s)
-                                                             : dense_apply(p, gy, gx, batch, true, s);
-        if (st != DCTPLUS_OK) return st;
-    }
-    if (!grho && !gv) return DCTPLUS_OK;
-    // split-K so that the grid has ~512+ workgroups and the partials stay modest
+    return DCTPLUS_OK;
+}
+
+// dl/drho and dl/dv with the Gram partials, G, G^T and the vectors in `work`
+// (gram_splits(n) * 4 n^2 + grad_tail_bytes(n) bytes, nothing needs to start at zero:
+// every kernel writes its whole output).
+static dctplus_status grad_launch(dctplus_plan_s *p, const float *y, const float *gy, int64_t batch, double *grho,
+                                  double *gv, void *work, int nsplit, hipStream_t s) {
+    const int n = (int)p->n;
     const int nt = (n + GT - 1) / GT;
-    const int tiles = nt * nt;
-    int nsplit = 512 / tiles;
-    if (nsplit < 1) nsplit = 1;
-    if (nsplit > 128) nsplit = 128;
-    while (nsplit > 1 && (size_t)nsplit * n * n * sizeof(float) > (size_t)256 << 20) nsplit >>= 1;
     int64_t rows_per = (batch + nsplit - 1) / nsplit;
     rows_per = (rows_per + GK - 1) / GK * GK;
     if (rows_per < GK) rows_per = GK;
     const size_t pbytes = (size_t)nsplit * n * n * sizeof(float);
-    const size_t gbytes = 2 * sizeof(double) * (size_t)n * n;
-    const size_t vbytes = 3 * sizeof(double) * n;
-    // the workspace may already hold a FAST/DENSE scratch from the gx call above,
-    // which has completed its use of it in stream order
-    dctplus_status st = ensure_work(p, pbytes + gbytes + vbytes);
-    if (st != DCTPLUS_OK) return st;
-    float *partial = (float *)p->work;
-    double *G = (double *)((char *)p->work + pbytes);
+    float *partial = (float *)work;
+    double *G = (double *)((char *)work + pbytes);
     double *GT = G + (size_t)n * n;
     double *rvec = GT + (size_t)n * n;
     double *qvec = rvec + n;
@@ -257,6 +260,51 @@ dctplus_status grad_apply(dctplus_plan_s *p, const float *y, const float *gy, in
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "gradient launch");
     return DCTPLUS_OK;
+}
+
+}  // namespace
+
+dctplus_status grad_apply(dctplus_plan_s *p, const float *y, const float *gy, int64_t batch, float *gx,
+                          double *grho, double *gv, hipStream_t s) {
+    const int n = (int)p->n;
+    dctplus_status st = grad_check(p, grho, gv);
+    if (st != DCTPLUS_OK) return st;
+    if (gx) {
+        st = (p->route == DCTPLUS_ROUTE_FAST) ? fast_apply(p, gy, gx, batch, true, s)
+                                              : dense_apply(p, gy, gx, batch, true, s);
+        if (st != DCTPLUS_OK) return st;
+    }
+    if (!grho && !gv) return DCTPLUS_OK;
+    const int nsplit = gram_splits(n, (size_t)256 << 20);
+    // the workspace may already hold a FAST/DENSE scratch from the gx call above,
+    // which has completed its use of it in stream order
+    st = ensure_work(p, (size_t)nsplit * n * n * sizeof(float) + grad_tail_bytes(n));
+    if (st != DCTPLUS_OK) return st;
+    return grad_launch(p, y, gy, batch, grho, gv, p->work, nsplit, s);
+}
+
+dctplus_status grad_apply_static(dctplus_plan_s *p, const float *y, const float *gy, int64_t batch, float *gx,
+                                 double *grho, double *gv, void *scratch, size_t scratch_bytes, hipStream_t s) {
+    const int n = (int)p->n;
+    dctplus_status st = grad_check(p, grho, gv);
+    if (st != DCTPLUS_OK) return st;
+    const bool need = grho || gv;
+    const size_t tail = grad_tail_bytes(n);
+    if (need && tail + sizeof(float) * (size_t)n * n > scratch_bytes)
+        return fail(DCTPLUS_EUNSUPPORTED,
+                    "n = %d needs %zu bytes of scratch for dl/drho and dl/dv; the static scratch holds %zu "
+                    "(n <= %d)", n, tail + sizeof(float) * (size_t)n * n, scratch_bytes, kStaticGradMaxN);
+    if (gx && !route_alloc_free(p))
+        return fail(DCTPLUS_EUNSUPPORTED, "dl/dx on this plan's route needs the plan workspace or a library "
+                                          "GEMM; use dctplus_grad");
+    if (gx) {
+        st = (p->route == DCTPLUS_ROUTE_FAST) ? fast_apply(p, gy, gx, batch, true, s)
+                                              : dense_apply(p, gy, gx, batch, true, s);
+        if (st != DCTPLUS_OK) return st;
+    }
+    if (!need) return DCTPLUS_OK;
+    const int nsplit = gram_splits(n, scratch_bytes - tail);
+    return grad_launch(p, y, gy, batch, grho, gv, scratch, nsplit, s);
 }
 
 }  // namespace dctplus

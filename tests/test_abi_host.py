@@ -104,6 +104,7 @@ def test_calls_on_null_plan_are_rejected(lib):
     assert lib.dctplus_forward(None, ctypes.c_void_p(16), ctypes.c_void_p(32), 4, None) == 1
     assert lib.dctplus_adjoint(None, ctypes.c_void_p(16), ctypes.c_void_p(32), 4, None) == 1
     assert lib.dctplus_grad(None, None, None, 4, None, None, None, None) == 1
+    assert lib.dctplus_grad_noalloc(None, None, None, 4, None, None, None, None) == 1
     assert lib.dctplus_plan_info(None, None, None, None, None, None) == 1
     lib.dctplus_plan_destroy(None)
     from paper_2409_08970_amd import _binding as B

@@ -1,0 +1,101 @@
+"""dctplus_grad_noalloc (the gradient with its scratch in a fixed device array)
+against dctplus_grad, both called through the C-ABI on the same inputs.
+
+dl/dx comes from the same adjoint kernels: bit-identical.  d rho and d v differ
+only in how many splits the FP32 Gram accumulation uses (fewer in the fixed
+scratch: up to 2048 batch rows per split at n = 256 and 65,536 signals), so the
+two agree within the gradient bar derived for the split accumulation: rounding of
+a running FP32 sum of m terms is about 2^-24 sqrt(m / 2) relative, 2e-6 at
+m = 2048; the bar is 1e-5 against max(|d rho|, ||d v||_inf), as for dctplus_grad
+against the oracle.  Two calls in a row, the second smaller (n and batch), so the
+second runs on what the first left in the array.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+TOLGRAD = 1e-5
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _grads(fn, plan, y, gy, n, batch, want_x):
+    torch = _torch()
+    gx = torch.full_like(gy, float("nan")) if want_x else None
+    grho = torch.full((1,), float("nan"), dtype=torch.float64, device="cuda")
+    gv = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    fn(plan.handle, y.data_ptr(), gy.data_ptr(), batch, gx.data_ptr() if want_x else 0, grho.data_ptr(),
+       gv.data_ptr())
+    torch.cuda.synchronize()
+    return (gx.cpu() if want_x else None), grho.item(), gv.cpu().numpy()
+
+
+def _case(n, batch, seed, route):
+    torch = _torch()
+    from paper_2409_08970_amd import Plan, dctplus_grad, dctplus_grad_noalloc
+    g = workloads.rng(seed)
+    v = workloads.unit_vector(g, n)
+    rho = 1.0
+    x = g.standard_normal((batch, n)).astype(np.float32)
+    plan = Plan(n, rho, v, route=route)
+    xt = torch.from_numpy(x).cuda()
+    y = plan.forward(xt)
+    gy = (torch.sign(y) / y.numel()).contiguous()
+    want_x = n <= 64
+    ref = _grads(dctplus_grad, plan, y, gy, n, batch, want_x)
+    got = _grads(dctplus_grad_noalloc, plan, y, gy, n, batch, want_x)
+    plan.close()
+    if want_x:
+        assert torch.equal(ref[0], got[0])
+    scale = max(abs(ref[1]), np.abs(ref[2]).max())
+    e_rho = abs(got[1] - ref[1]) / scale
+    e_v = np.abs(got[2] - ref[2]).max() / scale
+    print(f"n={n} batch={batch}: d rho {e_rho:.2e}, d v {e_v:.2e}", flush=True)
+    assert np.isfinite(got[1]) and np.all(np.isfinite(got[2]))
+    assert e_rho <= TOLGRAD and e_v <= TOLGRAD, (e_rho, e_v)
+    return x, v, rho, y, got
+
+
+@pytest.mark.gpu
+def test_noalloc_grad_matches_grad_two_calls():
+    # first call: the gradient workload's shape (many Gram stages per split)
+    _case(256, 65536, 41, "auto")
+    # second call, smaller: n = 64 (streaming dense route, dl/dx too), 1000 signals;
+    # also checked against the oracle's perturbation formula
+    x, v, rho, y, got = _case(64, 1000, 42, "dense")
+    mu, X = oracle.basis(64, rho, v)
+    y_ref = oracle.forward(X, x.astype(np.float64))
+    gy = np.sign(y.cpu().double().numpy()) / y.numel()
+    _, drho, dv = oracle.grad_perturbation(mu, X, rho, v, y_ref, gy)
+    scale = max(abs(drho), np.abs(dv).max())
+    assert abs(got[1] - drho) <= TOLGRAD * scale
+    assert np.abs(got[2] - dv).max() <= TOLGRAD * scale
+
+
+@pytest.mark.gpu
+def test_noalloc_grad_limits_are_refused_before_device_work():
+    torch = _torch()
+    from paper_2409_08970_amd import DctPlusError, Plan, dctplus_grad_noalloc
+    n = 1024
+    v = workloads.unit_vector(workloads.rng(43), n)
+    plan = Plan(n, 0.5, v, route="dense")
+    y = torch.zeros(8, n, device="cuda")
+    gy = torch.zeros_like(y)
+    grho = torch.full((1,), 7.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(DctPlusError) as ei:
+        dctplus_grad_noalloc(plan.handle, y.data_ptr(), gy.data_ptr(), 8, 0, grho.data_ptr(), 0)
+    assert ei.value.status == 4            # EUNSUPPORTED: n above the scratch limit
+    gx = torch.full_like(gy, 3.0)
+    with pytest.raises(DctPlusError) as ei:  # dl/dx on an FP32 dense plan above n = 64 needs the GEMM library
+        dctplus_grad_noalloc(plan.handle, y.data_ptr(), gy.data_ptr(), 8, gx.data_ptr(), 0, 0)
+    assert ei.value.status == 4
+    torch.cuda.synchronize()
+    assert grho.item() == 7.0 and bool((gx == 3.0).all())
+    plan.close()
