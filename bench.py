@@ -3,12 +3,17 @@
 A step is one forward (y = X^T x) plus one adjoint (x = X y) pass of the
 DCT+ transform over the whole batch of the shared-transform workload
 (n = 64, 2^20 AR(0.95) signals, random unit v, rho ~ U[0.1, 2]; FP32),
-inputs resident in HBM.  value = batch * n / (time per step): signal-samples
-per second through the round trip.  Beside it: the dense GFT (the paper's
-naive product) on the same GPU, with our MFMA kernel and with torch.matmul
-(hipBLASLt), the BF16-operand dense route, the n = 4096 large-graph workload,
-the roofline of the dominant kernel (HIP events on its launch stream), and
-the FP64 oracle timed on the host cores (a baseline, not a target).
+inputs resident in HBM.  The transform is applied as Thm 3.1 factors it: a
+DCT-II of every signal, then the product with the Cauchy factor
+diag(a) C(mu, lambda) diag(z) (split-BF16 MFMA products, FP32-accurate).
+value = batch * n / (time per step): signal-samples per second through the
+round trip.  Beside it: the dense GFT (the paper's naive product y = X^T x,
+the DCT folded into one matrix) on the same GPU, with our MFMA kernel and
+with torch.matmul, the BF16-operand dense route, the O(n log n) route, the
+large-graph workloads at n = 4096 and 16384 (with the FP64-vector roofline
+of the O(n log n) kernels), the roofline of the dominant kernel (HIP events
+on its launch stream), and the FP64 oracle timed on the host cores (a
+baseline, not a target).
 
 python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -25,35 +30,34 @@ METRIC = "signal-samples/s DCT+ fwd+bwd vs dense GFT, n=64 & 4096, FP32, rel err
 HBM_PEAK_GBS = 8000.0
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "dense_stream_n64_hbm_counters.md")
-STREAM_SOURCE = os.path.join(ROOT, "paper_2409_08970_amd", "csrc", "dense.hip")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "factored_stream_n64_hbm_counters.md")
 
 
-def kernel_source_hash(path, marker):
-    """sha256 of a kernel's source text: from the line holding `marker` to the
-    next line that is a lone closing brace."""
+def sources_hash(paths):
+    """sha256 over the full text of the kernel's source files, in the listed order."""
     import hashlib
-    lines = open(path).read().splitlines()
-    start = next(i for i, ln in enumerate(lines) if marker in ln)
-    end = next(i for i in range(start, len(lines)) if lines[i] == "}")
-    return hashlib.sha256("\n".join(lines[start:end + 1]).encode()).hexdigest()
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel_key):
     """HBM bytes per launch from the committed rocprofv3 counter summary (FETCH_SIZE
     and WRITE_SIZE per dispatch, each scaled by what the counter reads for a plain
-    device copy of known size), or None when the kernel's source has changed
-    since the counters were taken."""
+    device copy of known size), or None when any source file of the kernel has
+    changed since the counters were taken."""
     try:
         text = open(TRAFFIC_PROFILE).read()
         block = text.split("```json", 1)[1].split("```", 1)[0]
         rec = json.loads(block)
         k = rec["kernels"][kernel_key]
-        if kernel_source_hash(STREAM_SOURCE, rec["source_marker"]) != rec["source_sha256"]:
+        if sources_hash(rec["source_files"]) != rec["source_sha256"]:
             return None
         kib = k["fetch_kib"] * rec["fetch_scale"] + k["write_kib"] * rec["write_scale"]
         return kib * 1024.0
-    except (OSError, IndexError, KeyError, ValueError, StopIteration):
+    except (OSError, IndexError, KeyError, ValueError):
         return None
 
 
@@ -62,7 +66,10 @@ def _events(torch):
 
 
 def time_pair(torch, fwd, adj, steps, warmup):
-    """Times `steps` (fwd, adj) pairs; returns (ms/step, avg fwd ms, avg adj ms)."""
+    """Times `steps` (fwd, adj) pairs back to back, each launch bracketed by HIP events
+    on the current stream (the stream the library launches on).  Returns
+    (ms/step, mean fwd ms, mean adj ms, median fwd ms, median adj ms)."""
+    import statistics
     for _ in range(warmup):
         fwd()
         adj()
@@ -80,9 +87,20 @@ def time_pair(torch, fwd, adj, steps, warmup):
     t1.record()
     torch.cuda.synchronize()
     total = t0.elapsed_time(t1) / steps
-    f = sum(fe[k][0].elapsed_time(fe[k][1]) for k in range(steps)) / steps
-    a = sum(fe[k][1].elapsed_time(ae[k][1]) for k in range(steps)) / steps
-    return total, f, a
+    fl = [fe[k][0].elapsed_time(fe[k][1]) for k in range(steps)]
+    al = [fe[k][1].elapsed_time(ae[k][1]) for k in range(steps)]
+    return total, sum(fl) / steps, sum(al) / steps, statistics.median(fl), statistics.median(al)
+
+
+def fast_flops_per_signal(n, width):
+    """Algorithmic flops of one FAST-route transform of one signal (Alg. 1): the DCT-II
+    as a half-length complex FFT (5 (n/2) log2(n/2), FP32), the DST-I as a packed FFT of
+    length n (5 n log2 n), the oversampled grid DST of length 2n (5 2n log2 2n) and the
+    window gather (2 (w + 2) taps per output row); the last three in FP64."""
+    import math
+    fp32 = 5 * (n / 2) * math.log2(n / 2)
+    fp64 = 5 * n * math.log2(n) + 5 * 2 * n * math.log2(2 * n) + 2 * (width + 2) * n
+    return fp32, fp64
 
 
 def cpu_baseline(W, sample, min_seconds=10.0):
@@ -195,6 +213,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 19)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline DCT+ route (for profiler passes): no comparators, no CPU baseline")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run 3 device copies of the 256 MiB input (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -222,68 +242,85 @@ def main():
         print(json.dumps({"copy_probe_bytes_each_way": batch * n * 4}), flush=True)
         return
 
-    # the FP32-accurate DCT+ configurations; the headline is the faster one
-    cands = {}
-    for dt in ("f32", "f32split"):
-        pl = Plan(n, W["rho"], W["v"], route="auto", dtype=dt)
-        cands[dt] = (time_pair(torch, lambda: pl.forward(x, out=y), lambda: pl.adjoint(y, out=xr),
-                               args.steps, args.warmup), pl)
-    best = min(cands, key=lambda k: cands[k][0][0])
-    (ms, f_ms, a_ms), plan = cands[best]
-    for k, (_, pl) in cands.items():
-        if k != best:
-            pl.close()
+    # DCT+ as the paper factors it (Thm 3.1): a DCT-II of every signal (radix, in registers),
+    # then the product with the Cauchy factor diag(a) C(mu, lambda) diag(z) on MFMA with
+    # FP32-accurate split-BF16 products; the adjoint applies the transposed factors
+    plan = Plan(n, W["rho"], W["v"], route="dense", dtype="f32split", factored=True)
+    # the device reaches its sustained clocks only after some milliseconds of load: half a
+    # second of the headline's own launches (untimed) comes before anything is timed
+    t_end = time.perf_counter() + 0.5
+    while time.perf_counter() < t_end:
+        for _ in range(25):
+            plan.forward(x, out=y)
+            plan.adjoint(y, out=xr)
+        torch.cuda.synchronize()
+    ms, f_ms, a_ms, f_med, a_med = time_pair(torch, lambda: plan.forward(x, out=y), lambda: plan.adjoint(y, out=xr),
+                                             args.steps, args.warmup)
     route = plan.route
     value = batch * n / (ms * 1e-3)
     alg_bytes = 2 * batch * n * 4                       # read + write of the signals, per launch
-    launch_ms = 0.5 * (f_ms + a_ms)                     # forward and adjoint launch the same kernel
+    launch_ms = 0.5 * (f_ms + a_ms)                     # forward and adjoint: the same kernel, transposed
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
+    if args.headline_only:
+        args.no_extra = args.no_cpu = True
+        t0 = (float("nan"),) * 5
+    else:
+        # the factored form with FP32 MFMA products, for comparison
+        p0 = Plan(n, W["rho"], W["v"], route="dense", dtype="f32", factored=True)
+        t0 = time_pair(torch, lambda: p0.forward(x, out=y), lambda: p0.adjoint(y, out=xr), args.steps,
+                       args.warmup)
+        p0.close()
     result = {
         "metric": METRIC, "value": value, "unit": "signal-samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32" if best == "f32" else "f32 (bf16x3 split operands, fp32 accumulate)",
+        "vs_baseline": None, "dtype": "f32 (DCT-II in fp32; bf16x3 split operands, fp32 accumulate)",
         "data": "synthetic",
         "config": {"workload": f"shared-transform batch: n={n}, {batch} AR(0.95) signals, random unit v, "
-                               f"rho={W['rho']:.4f}", "route": route, "n": n, "batch": batch},
+                               f"rho={W['rho']:.4f}",
+                   "route": "DENSE factored (DCT-II, then the Cauchy factor)", "n": n, "batch": batch},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("k_dense_stream<64, 2>" if best == "f32split" else
-                                                 "k_dense_stream<64, 0>"),
+                     "traffic": measured_traffic("k_factored_stream<2>"),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-                     "kernel": "k_dense_stream<64> (forward and adjoint launches)", "avg_launch_ms": launch_ms,
+                     "kernel": "k_factored_stream<2> (forward and adjoint launches)", "avg_launch_ms": launch_ms,
+                     "median_launch_ms": 0.5 * (f_med + a_med), "launches_timed": 2 * args.steps,
                      "algorithmic_bytes_per_launch": alg_bytes},
-        "forward_ms": f_ms, "adjoint_ms": a_ms,
-        "dct_plus_configs": {k: {"ms_per_step": v[0][0], "value": batch * n / (v[0][0] * 1e-3)}
-                             for k, v in cands.items()},
+        "forward_ms": f_ms, "adjoint_ms": a_ms, "forward_median_ms": f_med, "adjoint_median_ms": a_med,
+        "dct_plus_configs": {"factored_f32split": {"ms_per_step": ms, "value": value},
+                             "factored_f32_mfma": {"ms_per_step": t0[0], "value": batch * n / (t0[0] * 1e-3),
+                                                   "median_launch_ms": 0.5 * (t0[3] + t0[4])}},
     }
-    print(f"dct+ {route}: {ms:.3f} ms/step (fwd {f_ms:.3f}, adj {a_ms:.3f})", file=sys.stderr, flush=True)
+    print(f"dct+ factored: {ms:.3f} ms/step (fwd {f_ms:.3f}, adj {a_ms:.3f})", file=sys.stderr, flush=True)
 
     if not args.no_extra:
         comp = {}
-        # dense GFT on the same GPU: our MFMA kernel, and the library GEMM
-        gp = Plan(n, W["rho"], W["v"], route="gft")
-        g_ms, _, _ = time_pair(torch, lambda: gp.forward(x, out=y), lambda: gp.adjoint(y, out=xr),
-                               args.steps, args.warmup)
-        comp["gft_mfma"] = {"ms_per_step": g_ms, "value": batch * n / (g_ms * 1e-3)}
-        XtT = torch.empty(n, n, device=dev)
-        Xt = torch.from_numpy(np.ascontiguousarray(
-            np.eye(n, dtype=np.float32))).to(dev)
-        gp.forward(Xt, out=XtT)                  # rows: X^T e_i -> X[i, :]
-        Xm = XtT.contiguous()                    # X (rows = spatial index)
-        XmT = Xm.t().contiguous()
-        l_ms, _, _ = time_pair(torch, lambda: torch.matmul(x, Xm, out=y), lambda: torch.matmul(y, XmT, out=xr),
-                               args.steps, args.warmup)
-        comp["gft_torch_matmul"] = {"ms_per_step": l_ms, "value": batch * n / (l_ms * 1e-3)}
-        gp.close()
+        # dense GFT (the paper's naive product y = X^T x) on the same GPU: our streaming MFMA
+        # kernel on X^T (split-BF16 and FP32 products), and the library GEMM
+        for key, dt in (("gft_mfma_f32split", "f32split"), ("gft_mfma_f32", "f32")):
+            gp = Plan(n, W["rho"], W["v"], route="gft", dtype=dt)
+            g = time_pair(torch, lambda: gp.forward(x, out=y), lambda: gp.adjoint(y, out=xr), args.steps,
+                          args.warmup)
+            comp[key] = {"ms_per_step": g[0], "value": batch * n / (g[0] * 1e-3),
+                         "median_launch_ms": 0.5 * (g[3] + g[4])}
+            if dt == "f32":
+                XtT = torch.empty(n, n, device=dev)
+                Xt = torch.from_numpy(np.ascontiguousarray(np.eye(n, dtype=np.float32))).to(dev)
+                gp.forward(Xt, out=XtT)                  # rows: X^T e_i -> X[i, :]
+                Xm = XtT.contiguous()                    # X (rows = spatial index)
+                XmT = Xm.t().contiguous()
+            gp.close()
+        l = time_pair(torch, lambda: torch.matmul(x, Xm, out=y), lambda: torch.matmul(y, XmT, out=xr),
+                      args.steps, args.warmup)
+        comp["gft_torch_matmul"] = {"ms_per_step": l[0], "value": batch * n / (l[0] * 1e-3)}
         bp = Plan(n, W["rho"], W["v"], route="dense", dtype="bf16")
-        b_ms, _, _ = time_pair(torch, lambda: bp.forward(x, out=y), lambda: bp.adjoint(y, out=xr),
-                               args.steps, args.warmup)
+        b_ms = time_pair(torch, lambda: bp.forward(x, out=y), lambda: bp.adjoint(y, out=xr),
+                         args.steps, args.warmup)[0]
         comp["dense_bf16_operands"] = {"ms_per_step": b_ms, "value": batch * n / (b_ms * 1e-3)}
         bp.close()
         # the O(n log n) route of Alg. 1 on the same workload
         fp = Plan(n, W["rho"], W["v"], route="fast")
-        f_ms2, _, _ = time_pair(torch, lambda: fp.forward(x, out=y), lambda: fp.adjoint(y, out=xr),
-                                max(3, args.steps // 4), 1)
+        f_ms2 = time_pair(torch, lambda: fp.forward(x, out=y), lambda: fp.adjoint(y, out=xr),
+                          max(3, args.steps // 4), 1)[0]
         comp["fast_route"] = {"ms_per_step": f_ms2, "value": batch * n / (f_ms2 * 1e-3)}
         fp.close()
         # the same workload at n = 32 (2^20 AR(0.95) signals), both FP32-accurate configurations
@@ -294,8 +331,8 @@ def main():
         n32 = {}
         for dt in ("f32", "f32split"):
             p32 = Plan(32, W32["rho"], W32["v"], route="auto", dtype=dt)
-            t32, _, _ = time_pair(torch, lambda: p32.forward(x32, out=y32), lambda: p32.adjoint(y32, out=r32),
-                                  args.steps, args.warmup)
+            t32 = time_pair(torch, lambda: p32.forward(x32, out=y32), lambda: p32.adjoint(y32, out=r32),
+                            args.steps, args.warmup)[0]
             n32[dt] = {"ms_per_step": t32, "value": x32.shape[0] * 32 / (t32 * 1e-3),
                        "hbm_gbs": 2 * 2 * x32.numel() * 4 / (t32 * 1e-3) / 1e9}
             p32.close()
@@ -310,17 +347,31 @@ def main():
             large = {}
             for rt in ("dense", "gft", "fast"):
                 p3 = Plan(nl, W3["rho"], W3["v"], route=rt)
-                t3, _, _ = time_pair(torch, lambda: p3.forward(x3, out=y3), lambda: p3.adjoint(y3, out=r3),
-                                     max(3, args.steps // 4), 2)
-                large[rt] = {"ms_per_step": t3, "value": 256 * nl / (t3 * 1e-3)}
+                t3 = time_pair(torch, lambda: p3.forward(x3, out=y3), lambda: p3.adjoint(y3, out=r3),
+                               max(20, args.steps), 2)
+                large[rt] = {"ms_per_step": t3[0], "value": 256 * nl / (t3[0] * 1e-3)}
+                if rt == "fast":
+                    # FP64-vector roofline of the FAST kernels (Alg. 1): algorithmic flops of
+                    # 256 signals per launch over the mean launch time (HIP events)
+                    f32f, f64f = fast_flops_per_signal(nl, 12)
+                    lm = 0.5 * (t3[1] + t3[2])
+                    ach = 256 * (f32f + f64f) / (lm * 1e-3) / 1e12
+                    large["fast_roofline"] = {
+                        "bound": "alu", "achieved": ach, "peak": 78.6, "unit": "TFLOP/s", "frac": ach / 78.6,
+                        "kernel": "k_fast_fwd / k_fast_adj", "avg_launch_ms": lm,
+                        "median_launch_ms": 0.5 * (t3[3] + t3[4]),
+                        "flops_per_signal": {"fp32": f32f, "fp64": f64f},
+                        "flop_formula": "5 (n/2) log2(n/2) [fp32 DCT] + 5 n log2 n [DST-I] + 5 (2n) log2(2n) "
+                                        "[grid DST] + 2 (w+2) n [window gather, w=12], fp64 except the DCT; "
+                                        "peak = FP64 vector 78.6 TFLOP/s (FP32 counted against it too)"}
                 p3.close()
             pa = Plan(nl, W3["rho"], W3["v"], route="auto")
             large["dct_plus_auto"] = {"route": pa.route, **large[pa.route]}
             pa.close()
             A = torch.randn(nl, nl, device=dev)
             At = A.t().contiguous()
-            t3, _, _ = time_pair(torch, lambda: torch.matmul(x3, A, out=y3), lambda: torch.matmul(y3, At, out=r3),
-                                 max(3, args.steps // 4), 2)
+            t3 = time_pair(torch, lambda: torch.matmul(x3, A, out=y3), lambda: torch.matmul(y3, At, out=r3),
+                           max(3, args.steps // 4), 2)[0]
             large["gft_torch_matmul"] = {"ms_per_step": t3, "value": 256 * nl / (t3 * 1e-3)}
             comp[f"n{nl}_workload"] = large
             del A, At, x3, y3, r3

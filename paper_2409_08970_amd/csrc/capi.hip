@@ -167,12 +167,16 @@ dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const d
         return fail(DCTPLUS_EUNSUPPORTED, "BF16 operands apply to the DENSE and GFT routes");
     if (o.dtype == DCTPLUS_F32_SPLIT && (n < 32 || n > 64))
         return fail(DCTPLUS_EUNSUPPORTED, "the split-BF16 mode supports n in {32, 64}");
+    if (o.dtype == DCTPLUS_F32_SPLIT && o.factored == 1 && n != 64)
+        return fail(DCTPLUS_EUNSUPPORTED, "the factored split-BF16 form supports n = 64");
 
     if (o.dtype == DCTPLUS_BF16 && (n < 32 || n > 64))
         return fail(DCTPLUS_EUNSUPPORTED, "BF16 dense routes support n in {32, 64}");
     if (o.factored != 0 && o.factored != 1) return fail(DCTPLUS_EINVAL, "factored must be 0 or 1");
-    if (o.factored && (route != DCTPLUS_ROUTE_DENSE || (o.dtype != DCTPLUS_F32 && o.dtype != DCTPLUS_BF16)))
-        return fail(DCTPLUS_EUNSUPPORTED, "the factored form is available on the DENSE route for F32 and BF16");
+    if (o.factored && (route != DCTPLUS_ROUTE_DENSE ||
+                       (o.dtype != DCTPLUS_F32 && o.dtype != DCTPLUS_BF16 && o.dtype != DCTPLUS_F32_SPLIT)))
+        return fail(DCTPLUS_EUNSUPPORTED,
+                    "the factored form is available on the DENSE route for F32, BF16 and F32_SPLIT");
 
     int dev = o.device;
     hipError_t e;

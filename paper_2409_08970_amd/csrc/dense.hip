@@ -17,6 +17,7 @@
 
 #include <new>
 
+#include "dct64.h"
 #include "fft.h"
 
 namespace dctplus {
@@ -25,6 +26,8 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
     // round to nearest even (finite inputs)
@@ -317,6 +320,73 @@ __global__ void __launch_bounds__(256) k_stream_image(const float *__restrict__ 
     }
 }
 
+// One tile's product on MFMA: acc[c] (output tile c, rows 16 c + 4 g + v of signal l16)
+// = sum over the lane's KQ contraction values b[q] against the A image in LDS.  `la` is
+// the lane index passed through an opaque copy by the caller (kept inside the tile loop).
+template <int N, int MODE, bool FENCED = false>
+__device__ __forceinline__ void stream_product(const float *b, const unsigned char *sa, int la, f4 *acc) {
+    using C = StreamCfg<N>;
+    constexpr int KQ = C::KQ, CT = C::CT;
+    constexpr int NS = CT * (KQ / 8);
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[c] = f4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (MODE == 0) {
+        const float4 *af = reinterpret_cast<const float4 *>(sa);
+#pragma unroll
+        for (int qq = 0; qq < KQ / 4; ++qq)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                const float4 a4 = af[(c * (KQ / 4) + qq) * 64 + la];
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.x, b[4 * qq + 0], acc[c], 0, 0, 0);
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.y, b[4 * qq + 1], acc[c], 0, 0, 0);
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.z, b[4 * qq + 2], acc[c], 0, 0, 0);
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.w, b[4 * qq + 3], acc[c], 0, 0, 0);
+            }
+    } else {
+        const bf8 *af = reinterpret_cast<const bf8 *>(sa);
+#pragma unroll
+        for (int st = 0; st < KQ / 8; ++st) {
+            // FP32 -> BF16 with the hardware conversion (round to nearest even, two values per
+            // v_cvt_pk_bf16_f32): the same bits as split3 / f2bf for finite values
+            bf8 bh, bm, bl;
+#pragma unroll
+            for (int e = 0; e < 8; e += 2) {
+                const f2v x = {b[8 * st + e], b[8 * st + e + 1]};
+                const bf2v h = __builtin_convertvector(x, bf2v);
+                bh[e] = h[0];
+                bh[e + 1] = h[1];
+                if constexpr (MODE == 2) {
+                    const f2v r = x - __builtin_convertvector(h, f2v);
+                    const bf2v m = __builtin_convertvector(r, bf2v);
+                    const bf2v l = __builtin_convertvector(r - __builtin_convertvector(m, f2v), bf2v);
+                    bm[e] = m[0];
+                    bm[e + 1] = m[1];
+                    bl[e] = l[0];
+                    bl[e + 1] = l[1];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                const int f = c * (KQ / 8) + st;
+                const bf8 ah = af[f * 64 + la];
+                if constexpr (MODE == 2) {
+                    const bf8 am = af[(NS + f) * 64 + la];
+                    const bf8 al = af[(2 * NS + f) * 64 + la];
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[c], 0, 0, 0);
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[c], 0, 0, 0);
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, acc[c], 0, 0, 0);
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, acc[c], 0, 0, 0);
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, acc[c], 0, 0, 0);
+                }
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[c], 0, 0, 0);
+                // FENCED: keep the operand reads of later output tiles from being hoisted
+                // (all of them in flight at once would hold 96 VGPRs)
+                if constexpr (FENCED) __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+}
+
 // MODE 0: FP32 MFMA.  MODE 1: BF16 operands.  MODE 2: FP32-accurate products from
 // three-piece BF16 splits of both operands, keeping the six cross products of
 // order >= 2^-16 (hh, hm, mh, mm, hl, lh) with FP32 accumulation.
@@ -324,8 +394,7 @@ template <int N, int MODE>
 __global__ void __launch_bounds__(256, 4) k_dense_stream(const float *__restrict__ in, float *__restrict__ out,
                                                       int64_t batch, const unsigned char *__restrict__ img) {
     using C = StreamCfg<N>;
-    constexpr int KQ = C::KQ, CT = C::CT, V4 = C::V4, D = C::kDepth;
-    constexpr int NS = CT * (KQ / 8);                // BF16 fragments per piece
+    constexpr int CT = C::CT, V4 = C::V4, D = C::kDepth;
     __shared__ __align__(16) unsigned char sa[stream_lds_bytes<N, MODE>()];
     // per-wave staging of one tile (16 rows of N/4 float4 chunks): tiles move between
     // HBM and registers as contiguous 1 KiB pieces and are re-laid out here
@@ -383,55 +452,7 @@ __global__ void __launch_bounds__(256, 4) k_dense_stream(const float *__restrict
         int la = lane;
         asm volatile("" : "+v"(la));
         f4 acc[CT];
-#pragma unroll
-        for (int c = 0; c < CT; ++c) acc[c] = f4{0.f, 0.f, 0.f, 0.f};
-        const float *b = reinterpret_cast<const float *>(bt);
-        if constexpr (MODE == 0) {
-            const float4 *af = reinterpret_cast<const float4 *>(sa);
-#pragma unroll
-            for (int qq = 0; qq < KQ / 4; ++qq)
-#pragma unroll
-                for (int c = 0; c < CT; ++c) {
-                    const float4 a4 = af[(c * (KQ / 4) + qq) * 64 + la];
-                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.x, b[4 * qq + 0], acc[c], 0, 0, 0);
-                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.y, b[4 * qq + 1], acc[c], 0, 0, 0);
-                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.z, b[4 * qq + 2], acc[c], 0, 0, 0);
-                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.w, b[4 * qq + 3], acc[c], 0, 0, 0);
-                }
-        } else {
-            const bf8 *af = reinterpret_cast<const bf8 *>(sa);
-#pragma unroll
-            for (int st = 0; st < KQ / 8; ++st) {
-                bf8 bh, bm, bl;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    if constexpr (MODE == 2) {
-                        uint16_t h, m, l;
-                        split3(b[8 * st + e], h, m, l);
-                        bh[e] = bits2bf(h);
-                        bm[e] = bits2bf(m);
-                        bl[e] = bits2bf(l);
-                    } else {
-                        bh[e] = bits2bf(f2bf(b[8 * st + e]));
-                    }
-                }
-#pragma unroll
-                for (int c = 0; c < CT; ++c) {
-                    const int f = c * (KQ / 8) + st;
-                    const bf8 ah = af[f * 64 + la];
-                    if constexpr (MODE == 2) {
-                        const bf8 am = af[(NS + f) * 64 + la];
-                        const bf8 al = af[(2 * NS + f) * 64 + la];
-                        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[c], 0, 0, 0);
-                        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[c], 0, 0, 0);
-                        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, acc[c], 0, 0, 0);
-                        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, acc[c], 0, 0, 0);
-                        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, acc[c], 0, 0, 0);
-                    }
-                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[c], 0, 0, 0);
-                }
-            }
-        }
+        stream_product<N, MODE>(reinterpret_cast<const float *>(bt), sa, la, acc);
         if (guarded) {
             const int64_t sig = tile * 16 + l16;
             if (sig < batch) {
@@ -479,6 +500,240 @@ __global__ void __launch_bounds__(256, 4) k_dense_stream(const float *__restrict
 #pragma unroll
         for (int v = 0; v < V4; ++v) b[v] = (sig < batch) ? src[4 * v + g] : f4{0.f, 0.f, 0.f, 0.f};
         compute_store(nfull, b, true);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Factored streaming kernel, n = 64: Thm 3.1 applied as the product of its
+// factors, y = M s_d with M = diag(a) C(mu, lambda) diag(z) and s_d = DCT-II(x)
+// (forward), x = DCT-III(M^T y) (adjoint).  The DCT runs in registers on the
+// four lanes holding a signal (dct64.h: a real 16-point DFT per lane, a 4 x 4
+// block transposition across the lane groups with v_permlane32_swap /
+// v_permlane16_swap, a radix-4 butterfly and rotation per frequency pair), the
+// product with M on MFMA.  Tiles, the ring of loads in flight, the staging of
+// tiles through LDS and the persistent grid are those of k_dense_stream.  The
+// MFMA contraction index follows the DCT's output slots (forward) and the
+// adjoint product's output rows are the inverse DCT's input slots, so the
+// factors meet without a further exchange.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void xpose_lane_groups(float R[16]) {
+    // R[4 b + e] of lane group g -> R[4 g' + e] of lane group b (block b of g' ...)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(R[4 * b + e]),
+                                                            __float_as_uint(R[4 * (b + 2) + e]), false, false);
+            R[4 * b + e] = __uint_as_float(r[0]);
+            R[4 * (b + 2) + e] = __uint_as_float(r[1]);
+        }
+#pragma unroll
+    for (int b = 0; b < 4; b += 2)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(R[4 * b + e]),
+                                                            __float_as_uint(R[4 * (b + 1) + e]), false, false);
+            R[4 * b + e] = __uint_as_float(r[0]);
+            R[4 * (b + 1) + e] = __uint_as_float(r[1]);
+        }
+}
+
+// Operand image of the factored kernel, laid out as k_stream_image's.
+//   forward: A = M; contraction slot q of lane group g is DCT coefficient d64::out_index(g, q).
+//   adjoint: A = M^T; output row 4 g + v of tile c is coefficient d64::out_index(g, 4 c + v),
+//            contraction slot q of lane group g is sample 16 (q / 4) + 4 g + q % 4 of y.
+// Lane constants of the DCT's frequency groups, [lane group g][group A, B] (k1 = 2 g + 1, 2 g + 2;
+// the second of lane group 3 is unused: its group is the real pair k1 = 0, 8).
+__global__ void k_factored_consts(d64::GroupConst *__restrict__ kc) {
+    const int t = threadIdx.x;
+    if (t < 8) kc[t] = d64::group_const((t >> 1) * 2 + 1 + (t & 1));
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_factored_image(const float *__restrict__ M, int adj,
+                                                        unsigned char *__restrict__ img) {
+    constexpr int N = 64;
+    using C = StreamCfg<N>;
+    constexpr int KQ = C::KQ, CT = C::CT;
+    constexpr int NS = CT * (KQ / 8);
+    // element (row m of output tile c, contraction slot q of lane group g)
+    auto aval = [&](int c, int m, int q, int g) -> float {
+        if (!adj) return M[(size_t)(16 * c + m) * N + d64::out_index(g, q)];
+        const int k = d64::out_index(m >> 2, 4 * c + (m & 3));
+        const int j = 16 * (q >> 2) + 4 * g + (q & 3);
+        return M[(size_t)j * N + k];
+    };
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x, nthr = gridDim.x * blockDim.x;
+    if constexpr (MODE == 0) {
+        float *af = reinterpret_cast<float *>(img);
+        for (int e = tid; e < CT * KQ * 64; e += nthr) {
+            const int q4 = e & 3, ln = (e >> 2) & 63, rest = e >> 8;
+            const int c = rest / (KQ / 4), qq = rest % (KQ / 4);
+            af[e] = aval(c, ln & 15, 4 * qq + q4, ln >> 4);
+        }
+    } else {
+        uint16_t *af = reinterpret_cast<uint16_t *>(img);
+        for (int e = tid; e < NS * 64 * 8; e += nthr) {
+            const int el = e & 7, ln = (e >> 3) & 63, f = e >> 9;
+            const int c = f / (KQ / 8), st = f % (KQ / 8);
+            uint16_t h, m, l;
+            split3(aval(c, ln & 15, 8 * st + el, ln >> 4), h, m, l);
+            af[e] = h;
+            af[NS * 512 + e] = m;
+            af[2 * NS * 512 + e] = l;
+        }
+    }
+}
+
+constexpr int kFactoredDepth = 2;   // tiles in flight per wave
+
+template <int MODE, bool ADJ>
+__global__ void __launch_bounds__(256, 4) k_factored_stream(const float *__restrict__ in, float *__restrict__ out,
+                                                         int64_t batch, const unsigned char *__restrict__ img,
+                                                         const d64::GroupConst *__restrict__ kc) {
+    constexpr int N = 64;
+    using C = StreamCfg<N>;
+    constexpr int CT = C::CT, V4 = C::V4, D = kFactoredDepth;
+    __shared__ __align__(16) unsigned char sa[stream_lds_bytes<N, MODE>()];
+    constexpr int CH = N / 4;
+    // per-wave staging tile, rows padded to 68 floats (272 B): chunk ch of row r at float
+    // 68 r + 4 ch, so the DCT's sample gather and scatter take immediate offsets from two
+    // lane bases
+    constexpr int RS = N + 4;
+    __shared__ __align__(16) float stage[4][16 * RS];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int l16 = lane & 15, g = lane >> 4;
+    float *stf = stage[tid >> 6];
+    f4 *st = reinterpret_cast<f4 *>(stf);
+    auto spos = [](int r, int ch) -> int { return r * (RS / 4) + ch; };
+    const int64_t nfull = batch / 16;
+    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    auto loadc = [&](int64_t tile, f4 *b) {
+        const int64_t t = tile < nfull ? tile : nfull - 1;
+        const f4 *src = reinterpret_cast<const f4 *>(in + t * 16 * N);
+#pragma unroll
+        for (int u = 0; u < V4; ++u) b[u] = src[64 * u + lane];
+    };
+    f4 ring[D][V4];
+    if (nfull > 0) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) loadc(wave0 + d * nwaves, ring[d]);
+    }
+    {
+        const f4 *src = reinterpret_cast<const f4 *>(img);
+        f4 *dstl = reinterpret_cast<f4 *>(sa);
+        for (int e = tid; e < stream_lds_bytes<N, MODE>() / 16; e += blockDim.x) dstl[e] = src[e];
+    }
+    __syncthreads();
+    // constants of this lane group's two frequency groups (k1 = 2 g + 1, 2 g + 2)
+    // the frequency groups' constants stay in LDS and are read per tile through an opaque
+    // index (held across the loop they would take 28 VGPRs)
+    __shared__ d64::GroupConst skc[8];
+    if (tid < 8) skc[tid] = kc[tid];
+    __syncthreads();
+
+    // one tile: b = its 16 x 64 samples as coalesced chunks (row r of the tile = signal);
+    // rows from `nvalid` on are not stored
+    auto tile_op = [&](int64_t tile, const f4 *b, int nvalid) {
+        int la = lane;
+        asm volatile("" : "+v"(la));
+        const d64::GroupConst kA = skc[2 * (la >> 4)], kB = skc[2 * (la >> 4) + 1];
+#pragma unroll
+        for (int u = 0; u < V4; ++u) {
+            const int L = 64 * u + lane;
+            st[spos(L / CH, L % CH)] = b[u];
+        }
+        __builtin_amdgcn_wave_barrier();
+        float R[16];
+        f4 acc[CT];
+        if constexpr (!ADJ) {
+            // DCT-II of signal l16: the lane's sixteen Makhoul-ordered samples
+            // samples 2 g + 8 m (m < 8) and 63 - 2 g - 8 (m - 8) (m >= 8) of row l16
+            float a[16];
+            const float *lo = stf + RS * l16 + 2 * g, *hi = stf + RS * l16 + 63 - 2 * g;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                a[m] = lo[8 * m];
+                a[m + 8] = hi[-8 * m];
+            }
+            __builtin_amdgcn_wave_barrier();
+            d64::rdft16(a, R);
+            xpose_lane_groups(R);
+            float X[16];
+            d64::group_fwd(R, 0, kA, X);
+            if (g < 3) d64::group_fwd(R, 2, kB, X + 8);
+            else d64::special_fwd(R, X + 8);
+            stream_product<N, MODE, true>(X, sa, la, acc);
+            // outputs 16 c + 4 g .. + 3 of row l16 are chunk 4 c + g
+#pragma unroll
+            for (int c = 0; c < CT; ++c) st[spos(l16, 4 * c + g)] = acc[c];
+        } else {
+            // M^T y: the lane's y samples 16 (q / 4) + 4 g + q % 4 are chunks 4 v + g
+            f4 bv[V4];
+#pragma unroll
+            for (int v = 0; v < V4; ++v) bv[v] = st[spos(l16, 4 * v + g)];
+            __builtin_amdgcn_wave_barrier();
+            stream_product<N, MODE, true>(reinterpret_cast<const float *>(bv), sa, la, acc);
+            float X[16];
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) X[4 * c + v] = acc[c][v];
+            d64::group_adj(X, kA, R, 0);
+            if (g < 3) d64::group_adj(X + 8, kB, R, 2);
+            else d64::special_adj(X + 8, R);
+            xpose_lane_groups(R);
+            float a[16];
+            d64::rdft16_t(R, a);
+            float *lo = stf + RS * l16 + 2 * g, *hi = stf + RS * l16 + 63 - 2 * g;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                lo[8 * m] = a[m];
+                hi[-8 * m] = a[m + 8];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        f4 *dst = reinterpret_cast<f4 *>(out + tile * 16 * N);
+        if (nvalid == 16) {
+#pragma unroll
+            for (int u = 0; u < V4; ++u) {
+                const int L = 64 * u + lane;
+                dst[L] = st[spos(L / CH, L % CH)];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < V4; ++u) {
+                const int L = 64 * u + lane;
+                if (L / CH < nvalid) dst[L] = st[spos(L / CH, L % CH)];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+    if (nfull > 0) {
+        int64_t base = wave0;
+        for (; base + (D - 1) * nwaves < nfull; base += D * nwaves) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                tile_op(base + d * nwaves, ring[d], 16);
+                loadc(base + (d + D) * nwaves, ring[d]);
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < D - 1; ++d)
+            if (base + d * nwaves < nfull) tile_op(base + d * nwaves, ring[d], 16);
+    }
+    if (nfull * 16 < batch && wave0 == nfull % nwaves) {
+        // the ragged last tile: rows past the batch read as zeros and are not stored
+        const int nvalid = (int)(batch - nfull * 16);
+        const f4 *src = reinterpret_cast<const f4 *>(in + nfull * 16 * N);
+        f4 b[V4];
+#pragma unroll
+        for (int u = 0; u < V4; ++u) {
+            const int L = 64 * u + lane;
+            b[u] = (L / CH < nvalid) ? src[L] : f4{0.f, 0.f, 0.f, 0.f};
+        }
+        tile_op(nfull, b, nvalid);
     }
 }
 
@@ -776,6 +1031,22 @@ int stream_blocks(int64_t ntiles) {
     return (int)(want < cap ? want : cap);
 }
 
+template <int MODE, bool ADJ>
+int factored_blocks(int64_t ntiles) {
+    static int cap = 0;
+    if (cap == 0) {
+        int per = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_factored_stream<MODE, ADJ>, 256, 0) != hipSuccess ||
+            per <= 0) {
+            (void)hipGetLastError();
+            per = 2;
+        }
+        cap = per * num_cus();
+    }
+    const int64_t want = (ntiles + 3) / 4;
+    return (int)(want < cap ? want : cap);
+}
+
 template <int N, bool BF>
 void launch_small(const dctplus_plan_s *p, const float *in, float *out, int64_t batch, int adj, int pre,
                   hipStream_t s) {
@@ -808,8 +1079,34 @@ dctplus_status build_stream_image(dctplus_plan_s *p, hipStream_t s) {
     return DCTPLUS_OK;
 }
 
+// Factored-kernel operand images (forward: M, adjoint: M^T) for factored plans with n = 64.
+template <int MODE>
+dctplus_status build_factored_image(dctplus_plan_s *p, hipStream_t s) {
+    constexpr size_t bytes = stream_lds_bytes<64, MODE>();
+    hipError_t e = hipMalloc(&p->simg, 2 * bytes + 8 * sizeof(d64::GroupConst));
+    if (e != hipSuccess) {
+        p->simg = nullptr;
+        (void)hipGetLastError();
+        return fail(DCTPLUS_ENOMEM, "hipMalloc for the factored operand images failed");
+    }
+    p->simg_bytes = bytes;
+    unsigned char *img = (unsigned char *)p->simg;
+    for (int adj = 0; adj < 2; ++adj)
+        hipLaunchKernelGGL((k_factored_image<MODE>), dim3(16), dim3(256), 0, s, (const float *)p->t.mt32, adj,
+                           img + adj * bytes);
+    hipLaunchKernelGGL(k_factored_consts, dim3(1), dim3(64), 0, s, (d64::GroupConst *)(img + 2 * bytes));
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "factored operand images");
+    return DCTPLUS_OK;
+}
+
 dctplus_status stream_images(dctplus_plan_s *p, hipStream_t s) {
     const int n = (int)p->n;
+    if (!p->t.folded && n == 64) {
+        if (p->dtype == DCTPLUS_F32_SPLIT) return build_factored_image<2>(p, s);
+        if (p->dtype == DCTPLUS_F32) return build_factored_image<0>(p, s);
+        return DCTPLUS_OK;
+    }
     if (!p->t.folded || n < 16 || n > 64) return DCTPLUS_OK;
     if (p->dtype == DCTPLUS_F32_SPLIT) return n == 32 ? build_stream_image<32, 2>(p, s) : build_stream_image<64, 2>(p, s);
     if (p->dtype == DCTPLUS_BF16) return n == 32 ? build_stream_image<32, 1>(p, s) : build_stream_image<64, 1>(p, s);
@@ -918,9 +1215,27 @@ dctplus_status dense_apply(dctplus_plan_s *p, const void *inv, void *outv, int64
         if (bf && n == 16) return fail(DCTPLUS_EUNSUPPORTED, "BF16 dense route needs n >= 32");
         // the streaming kernel moves float4s: it needs 16-byte aligned signal arrays
         const bool vec_ok = ((((uintptr_t)in) | ((uintptr_t)out)) & 15) == 0;
-        if (split && (!p->t.folded || !vec_ok || n < 32))
-            return fail(DCTPLUS_EUNSUPPORTED, "the split-BF16 mode needs n in {32, 64} and 16-byte aligned arrays");
-        if (!p->t.folded || !vec_ok) {
+        if (split && (!vec_ok || n < 32 || (!p->t.folded && n != 64)))
+            return fail(DCTPLUS_EUNSUPPORTED, "the split-BF16 mode needs n in {32, 64} (factored: n = 64) and "
+                                              "16-byte aligned arrays");
+        if (!p->t.folded && n == 64 && vec_ok && !bf) {
+            // the factored form: DCT in registers, then the Cauchy factor on MFMA
+            const int64_t ntiles = (batch + 15) / 16;
+            if (!p->simg) return fail(DCTPLUS_EDEVICE, "no factored operand image on this plan");
+            const unsigned char *img = (const unsigned char *)p->simg + (adj ? p->simg_bytes : 0);
+            const d64::GroupConst *kc = (const d64::GroupConst *)((const unsigned char *)p->simg + 2 * p->simg_bytes);
+#define DCTPLUS_FACTORED(MM, AA)                                                                        \
+    hipLaunchKernelGGL((k_factored_stream<MM, AA>), dim3(factored_blocks<MM, AA>(ntiles)), dim3(256), 0, s, in, \
+                       out, batch, img, kc)
+            if (split) {
+                if (adj) DCTPLUS_FACTORED(2, true);
+                else DCTPLUS_FACTORED(2, false);
+            } else {
+                if (adj) DCTPLUS_FACTORED(0, true);
+                else DCTPLUS_FACTORED(0, false);
+            }
+#undef DCTPLUS_FACTORED
+        } else if (!p->t.folded || !vec_ok) {
             if (!bf) {
                 if (n == 16) launch_small<16, false>(p, in, out, batch, adj, pre, s);
                 else if (n == 32) launch_small<32, false>(p, in, out, batch, adj, pre, s);

@@ -87,14 +87,16 @@ def test_plan_rejects_bad_options_on_host(lib):
     o.dtype = B.DCTPLUS_BF16
     o.route = B.DCTPLUS_ROUTE_FAST
     assert B.dctplus_plan(64, 1.0, v, o, check=False)[0] == B.DCTPLUS_EUNSUPPORTED
-    # the factored form: 0 or 1, DENSE route, F32 or BF16 only
+    # the factored form: 0 or 1, DENSE route, F32, BF16 or F32_SPLIT (split: n = 64 only)
     for route, dtype, fac, expect in [(B.DCTPLUS_ROUTE_DENSE, B.DCTPLUS_F32, 2, B.DCTPLUS_EINVAL),
                                       (B.DCTPLUS_ROUTE_GFT, B.DCTPLUS_F32, 1, B.DCTPLUS_EUNSUPPORTED),
-                                      (B.DCTPLUS_ROUTE_DENSE, B.DCTPLUS_F64, 1, B.DCTPLUS_EUNSUPPORTED),
-                                      (B.DCTPLUS_ROUTE_DENSE, B.DCTPLUS_F32_SPLIT, 1, B.DCTPLUS_EUNSUPPORTED)]:
+                                      (B.DCTPLUS_ROUTE_DENSE, B.DCTPLUS_F64, 1, B.DCTPLUS_EUNSUPPORTED)]:
         o = B.dctplus_default_opts()
         o.route, o.dtype, o.factored = route, dtype, fac
         assert B.dctplus_plan(64, 1.0, v, o, check=False)[0] == expect, (route, dtype, fac)
+    o = B.dctplus_default_opts()
+    o.route, o.dtype, o.factored = B.DCTPLUS_ROUTE_DENSE, B.DCTPLUS_F32_SPLIT, 1
+    assert B.dctplus_plan(32, 1.0, np.ones(32), o, check=False)[0] == B.DCTPLUS_EUNSUPPORTED
     # null v and null output pointer
     assert lib.dctplus_plan(64, 1.0, None, None, None, ctypes.byref(ctypes.c_void_p())) == 1
     assert lib.dctplus_plan(64, 1.0, None, None, None, None) == 1

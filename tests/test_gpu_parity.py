@@ -378,14 +378,71 @@ def test_f32_split_bf16_products(route, n, kind):
     p.close()
 
 
-@pytest.mark.parametrize("route", ["fast", "dense", "gft", "dense-f32split"])
+@pytest.mark.parametrize("kind", ["dense", "loop0", "loopn", "edge", "negative"])
+def test_factored_split_n64(kind):
+    """The factored form at n = 64 with split-BF16 products (DCT-II in registers, then
+    the Cauchy factor on MFMA): held to the FP32 bar, on a ragged batch with tiny and
+    huge signals."""
+    n = 64
+    rho, v = case(n, kind)
+    x = workloads.ar1(np.random.default_rng(14), 333, n, 0.95)
+    x[5] *= 1e-30
+    x[6] *= 1e30
+    fwd, adj = reference(n, rho, v)
+    p = make_plan(n, rho, v, "dense-factored", dtype="f32split")
+    assert relerr(run(p, x), fwd(x.astype(np.float64))) <= TOL32
+    assert relerr(run(p, x, adjoint=True), adj(x.astype(np.float64))) <= TOL32
+    p.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f32split"])
+def test_factored_n64_batch_edges_and_alignment(dtype):
+    """Factored n = 64: batches around the 16-signal tile and the 4-tile grid
+    granule; arrays that are only 4-byte aligned take the LDS-tile kernel (FP32) or
+    are refused (split products need 16-byte alignment)."""
+    torch = _torch()
+    from paper_2409_08970_amd import _binding as B
+    n = 64
+    rho, v = case(n, "dense")
+    fwd, adj = reference(n, rho, v)
+    p = make_plan(n, rho, v, "dense-factored", dtype=dtype)
+    for batch in (1, 15, 16, 17, 63, 64, 65, 1000):
+        x = np.random.default_rng(batch).standard_normal((batch, n)).astype(np.float32)
+        assert relerr(run(p, x), fwd(x.astype(np.float64))) <= TOL32, batch
+        assert relerr(run(p, x, adjoint=True), adj(x.astype(np.float64))) <= TOL32, batch
+    xs = np.random.default_rng(9).standard_normal((40, n)).astype(np.float32)
+    buf = torch.zeros(40 * n + 2, device="cuda")
+    buf[1:1 + 40 * n] = torch.from_numpy(xs.reshape(-1)).cuda()
+    outb = torch.zeros(40 * n + 2, device="cuda")
+    st = B.dctplus_forward(p.handle, buf.data_ptr() + 4, outb.data_ptr() + 4, 40, check=False)
+    if dtype == "f32":
+        assert st == B.DCTPLUS_OK
+        torch.cuda.synchronize()
+        yo = outb[1:1 + 40 * n].cpu().double().numpy().reshape(40, n)
+        assert relerr(yo, fwd(xs.astype(np.float64))) <= TOL32
+    else:
+        assert st == B.DCTPLUS_EUNSUPPORTED
+    # determinism: repeated calls give the same bits
+    xt = torch.randn(517, n, device="cuda")
+    a, b = p.forward(xt), p.forward(xt)
+    c, d = p.adjoint(a), p.adjoint(a)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(c, d)
+    p.close()
+
+
+@pytest.mark.parametrize("route", ["fast", "dense", "gft", "dense-f32split", "dense-factored-f32",
+                                   "dense-factored-f32split"])
 def test_full_size_workload2_sampled(route):
     """Workload-2 launch shape (2^20 AR(0.95) signals, n = 64): every output
     row runs on the GPU; 2048 sampled signals are checked against Jacobi."""
     torch = _torch()
     W = workloads.workload2(64)
     n, rho, v, x = W["n"], W["rho"], W["v"], W["x"]
-    rt, _, dt = route.partition("-")
+    if route.startswith("dense-factored"):
+        rt, dt = "dense-factored", route.rsplit("-", 1)[1]
+    else:
+        rt, _, dt = route.partition("-")
     p = make_plan(n, rho, v, rt, dtype=dt or "f32")
     xt = torch.from_numpy(x).cuda()
     y = p.forward(xt)
