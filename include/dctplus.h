@@ -34,9 +34,16 @@
  *     On any non-OK status no output has been written (argument errors are
  *     detected before any device work).  dctplus_last_error() gives a
  *     thread-local message for the last failure.
- *   - A plan is immutable after creation and may be used concurrently from
- *     several streams, except that the gradient and selection calls use the
- *     plan's workspace and must not overlap on one plan.
+ *   - A plan is immutable after creation (its tables) and may be used
+ *     concurrently from several streams.  Routes that need scratch memory
+ *     (FAST with a per-signal buffer too large for LDS, the factored DENSE form
+ *     above n = 64, the gradient) keep one workspace per stream handle in the
+ *     plan: calls on different streams never share it, calls on one stream are
+ *     ordered by the stream.  The first such call on a stream, or a larger batch
+ *     than before, allocates (after waiting for that stream's earlier work):
+ *     make one call per stream before capturing such a route into a graph.
+ *     Selection plans have one work-queue counter: calls on one selection plan
+ *     must not overlap.
  */
 #ifndef DCTPLUS_H
 #define DCTPLUS_H
@@ -132,7 +139,7 @@ dctplus_status dctplus_adjoint(dctplus_plan_t plan, const void *y, void *x, int6
  * With G = sum_b gy_b y_b^T, A_ik = G_ik / (mu_i - mu_k) (A_ii = 0) and
  * w = X^T v:  dl/drho = w^T A w,  dl/dv = rho X (A + A^T) w  (first-order
  * eigenvector perturbation of L x_i = mu_i x_i, with Lemma 4.2 for w).
- * Uses the plan's workspace: calls on one plan must not overlap.
+ * Uses the workspace of `stream` in the plan (see the conventions above).
  * Errors (all detected before any device work, so nothing is written):
  *   EUNSUPPORTED  grho or gv requested with n > 4096;
  *   EDEGENERATE   grho or gv requested on a plan with a double eigenvalue (a secular
@@ -155,9 +162,9 @@ dctplus_status dctplus_grad(dctplus_plan_t plan, const void *y, const void *gy, 
  * Limits (EUNSUPPORTED, before any device work):
  *   - grho or gv requested with n > 512 (the scratch holds the n x n G and G^T
  *     in FP64 plus at least one n x n FP32 partial);
- *   - gx requested on a plan whose adjoint needs the plan workspace or the GEMM
- *     library: FP32 DENSE/GFT plans with n > 64, and FAST plans whose per-signal
- *     buffer does not fit in LDS.
+ *   - gx requested on a plan whose adjoint needs a workspace: DENSE plans in the
+ *     factored form with n > 64, and FAST plans whose per-signal buffer does not fit
+ *     in LDS.
  * Every call on one GPU shares that GPU's array: calls that overlap in time on
  * one GPU (different streams, threads or plans) race and give wrong results;
  * order them (one stream, or events).

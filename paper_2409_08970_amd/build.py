@@ -15,8 +15,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result", f"-I{INCLUDE}",
 ]
-# the FP32 dense product for n > 64 is a plain GEMM and goes to hipBLASLt
-LIBS = ["-L/opt/rocm/lib", "-lhipblaslt"]
+LIBS = []
 
 
 def sources():

@@ -32,24 +32,41 @@ dctplus_status hip_fail(hipError_t e, const char *what) {
     return fail(DCTPLUS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-dctplus_status ensure_work(dctplus_plan_s *p, size_t bytes) {
-    if (p->work_bytes >= bytes) return DCTPLUS_OK;
-    if (p->work) {
-        // earlier stream-ordered users of the old buffer must be done before it goes
-        hipError_t e = hipDeviceSynchronize();
-        if (e != hipSuccess) return hip_fail(e, "synchronize before workspace growth");
-        (void)hipFree(p->work);
-        p->work = nullptr;
-        p->work_bytes = 0;
+dctplus_status stream_work(dctplus_plan_s *p, hipStream_t s, size_t bytes, void **out) {
+    std::lock_guard<std::mutex> lock(p->work_mu);
+    dctplus_plan_s::StreamWork *w = nullptr;
+    for (auto &e : p->works)
+        if (e.stream == s) w = &e;
+    if (!w) {
+        p->works.push_back({s, nullptr, 0});
+        w = &p->works.back();
     }
-    hipError_t e = hipMalloc(&p->work, bytes);
-    if (e != hipSuccess) {
-        p->work = nullptr;
-        (void)hipGetLastError();
-        return fail(DCTPLUS_ENOMEM, "hipMalloc(%zu) for the workspace failed", bytes);
+    if (w->bytes < bytes) {
+        if (w->ptr) {
+            // this stream's earlier calls must be done with the old buffer before it goes
+            hipError_t e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(e, "synchronize before workspace growth");
+            (void)hipFree(w->ptr);
+            w->ptr = nullptr;
+            w->bytes = 0;
+        }
+        hipError_t e = hipMalloc(&w->ptr, bytes);
+        if (e != hipSuccess) {
+            w->ptr = nullptr;
+            (void)hipGetLastError();
+            return fail(DCTPLUS_ENOMEM, "hipMalloc(%zu) for the workspace failed", bytes);
+        }
+        w->bytes = bytes;
     }
-    p->work_bytes = bytes;
+    *out = w->ptr;
     return DCTPLUS_OK;
+}
+
+void release_works(dctplus_plan_s *p) {
+    std::lock_guard<std::mutex> lock(p->work_mu);
+    for (auto &e : p->works)
+        if (e.ptr) (void)hipFree(e.ptr);
+    p->works.clear();
 }
 
 // Device address of this GPU's copy of `scratch`, looked up on the first call
@@ -78,9 +95,9 @@ static dctplus_status scratch_ptr(int dev, void **out) {
 
 bool route_alloc_free(const dctplus_plan_s *p) {
     if (p->route == DCTPLUS_ROUTE_FAST) return fast_in_lds(p);
-    // dense routes: FP64 and n <= 64 run our kernels without workspace; FP32 above
-    // n = 64 calls the GEMM library (and the factored form a DCT pass in the workspace)
-    return p->dtype == DCTPLUS_F64 || p->n <= 64;
+    // dense routes need a workspace only for the factored form above n = 64 (the DCT
+    // pass writes its output there before the product)
+    return p->t.folded || p->n <= 64;
 }
 
 static bool aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
@@ -326,7 +343,7 @@ void dctplus_plan_destroy(dctplus_plan_t p) {
     if (p->t.mt16) (void)hipFree(p->t.mt16);
     if (p->t.mt64) (void)hipFree(p->t.mt64);
     dense_release(p);
-    if (p->work) (void)hipFree(p->work);
+    release_works(p);
     if (p->dev_mem) (void)hipFree(p->dev_mem);
     if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);
     delete p;

@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <vector>
+
 #include "dctplus.h"
 
 namespace dctplus {
@@ -72,9 +75,16 @@ struct dctplus_plan_s {
     int factored;             // DENSE route keeps the DCT and the Cauchy factor apart
     void *dev_mem;            // one allocation holding every table
     size_t dev_bytes;
-    void *work;               // lazily grown workspace (FFT scratch for large n, gradient)
-    size_t work_bytes;
-    void *blas;               // hipBLASLt set-up of the FP32 dense product for n > 64 (plain GEMM)
+    // workspaces (FAST-route scratch for large n, the factored route's DCT output above
+    // n = 64, gradient partials): one per stream handle, grown on demand, so calls on
+    // different streams never share one
+    struct StreamWork {
+        hipStream_t stream;
+        void *ptr;
+        size_t bytes;
+    };
+    std::mutex work_mu;
+    std::vector<StreamWork> works;
     void *simg;               // LDS images of the streaming kernel's operands (forward, adjoint), n <= 64
     size_t simg_bytes;        // bytes of one image
     dctplus::PlanTables t;
@@ -102,5 +112,7 @@ dctplus_status grad_apply_static(dctplus_plan_s *p, const float *y, const float 
 bool route_alloc_free(const dctplus_plan_s *p);
 bool fast_in_lds(const dctplus_plan_s *p);
 dctplus_status plan_build(dctplus_plan_s *p, const double *v_host, hipStream_t s);
-dctplus_status ensure_work(dctplus_plan_s *p, size_t bytes);
+// the workspace of stream s, at least `bytes` long (grows it: waits for s, frees, allocates)
+dctplus_status stream_work(dctplus_plan_s *p, hipStream_t s, size_t bytes, void **out);
+void release_works(dctplus_plan_s *p);
 }  // namespace dctplus

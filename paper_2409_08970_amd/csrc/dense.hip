@@ -13,8 +13,6 @@
 // wave multiplies 16 of them by P, whose B fragments stay in VGPRs for the
 // whole persistent loop.  For n >= 128 a tiled GEMM with P staged through LDS
 // is used, with the DCT as a separate pass.
-#include <hipblaslt/hipblaslt.h>
-
 #include <new>
 
 #include "dct64.h"
@@ -904,97 +902,110 @@ __global__ void __launch_bounds__(256) k_gemm64(const double *__restrict__ A, co
             }
 }
 
-// FP32 dense product for n > 64: a plain GEMM, run by hipBLASLt.  One handle,
-// two matmul descriptors (forward: D = P X, adjoint: D = P^T Y in column-major
-// terms) and, per direction, the layouts and algorithm of the last batch size.
-struct BlasLtPlan {
-    hipblasLtHandle_t h = nullptr;
-    hipblasLtMatmulDesc_t desc[2] = {nullptr, nullptr};
-    hipblasLtMatmulPreference_t pref = nullptr;
-    void *ws = nullptr;
-    size_t ws_bytes = 0;
-    struct Cached {
-        int64_t batch = -1;
-        hipblasLtMatrixLayout_t a = nullptr, b = nullptr, d = nullptr;
-        hipblasLtMatmulAlgo_t algo;
-    } c[2];
-};
+// FP32 dense product for n > 64 (Thm 3.1's product with the n x n factor P):
+//   C[m][j] = sum_k A[m][k] B(k, j),  B(k, j) = P[j][k] (TRANSB: forward, y = P s)
+//                                     or       P[k][j] (adjoint, x = P^T y),
+// A = the [M x K] signals (row-major), C = [M x N] (row-major), K = N = n.
+// BM x BN output tiles per workgroup (2 x 2 waves), k-steps of 16 through LDS with
+// the next step's operands loaded into registers while the current one is
+// multiplied; FP32 MFMA 16x16x4.  The contraction index is permuted inside each
+// k-step (lane group g supplies k = 4 g + s to the s-th of four MFMAs), so a lane
+// reads its four operand values of a row with one 16-byte LDS read; rows are
+// padded to 20 floats, which makes those reads conflict-free.  The adjoint's P is
+// transposed on its way into LDS.  n must be a multiple of 64 (or of BN); rows of
+// A and C past M are not read or written.
+constexpr int GKS = 16;      // k per step
+constexpr int GPAD = 20;     // LDS row stride (floats)
 
-void blaslt_release(BlasLtPlan *b) {
-    if (!b) return;
-    for (auto &c : b->c) {
-        if (c.a) hipblasLtMatrixLayoutDestroy(c.a);
-        if (c.b) hipblasLtMatrixLayoutDestroy(c.b);
-        if (c.d) hipblasLtMatrixLayoutDestroy(c.d);
-    }
-    for (auto d : b->desc)
-        if (d) hipblasLtMatmulDescDestroy(d);
-    if (b->pref) hipblasLtMatmulPreferenceDestroy(b->pref);
-    if (b->h) hipblasLtDestroy(b->h);
-    if (b->ws) (void)hipFree(b->ws);
-    delete b;
-}
-
-dctplus_status blaslt_create(int n, BlasLtPlan **out) {
-    BlasLtPlan *b = new (std::nothrow) BlasLtPlan();
-    if (!b) return fail(DCTPLUS_ENOMEM, "host allocation failed");
-    b->ws_bytes = size_t(32) << 20;
-    bool ok = hipMalloc(&b->ws, b->ws_bytes) == hipSuccess;
-    if (!ok) {
-        b->ws = nullptr;
-        (void)hipGetLastError();
-        blaslt_release(b);
-        return fail(DCTPLUS_ENOMEM, "hipMalloc for the GEMM workspace failed");
-    }
-    ok = hipblasLtCreate(&b->h) == HIPBLAS_STATUS_SUCCESS;
-    const int32_t ops[2][2] = {{HIPBLAS_OP_T, HIPBLAS_OP_N}, {HIPBLAS_OP_N, HIPBLAS_OP_N}};
-    for (int d = 0; ok && d < 2; ++d) {
-        ok = hipblasLtMatmulDescCreate(&b->desc[d], HIPBLAS_COMPUTE_32F, HIP_R_32F) == HIPBLAS_STATUS_SUCCESS &&
-             hipblasLtMatmulDescSetAttribute(b->desc[d], HIPBLASLT_MATMUL_DESC_TRANSA, &ops[d][0], sizeof(int32_t)) ==
-                 HIPBLAS_STATUS_SUCCESS &&
-             hipblasLtMatmulDescSetAttribute(b->desc[d], HIPBLASLT_MATMUL_DESC_TRANSB, &ops[d][1], sizeof(int32_t)) ==
-                 HIPBLAS_STATUS_SUCCESS;
-    }
-    const uint64_t wsb = b->ws_bytes;
-    ok = ok && hipblasLtMatmulPreferenceCreate(&b->pref) == HIPBLAS_STATUS_SUCCESS &&
-         hipblasLtMatmulPreferenceSetAttribute(b->pref, HIPBLASLT_MATMUL_PREF_MAX_WORKSPACE_BYTES, &wsb, sizeof(wsb)) ==
-             HIPBLAS_STATUS_SUCCESS;
-    if (!ok) {
-        blaslt_release(b);
-        return fail(DCTPLUS_EDEVICE, "hipBLASLt set-up failed for n = %d", n);
-    }
-    *out = b;
-    return DCTPLUS_OK;
-}
-
-// D (n x batch, column-major, ld n) = op(P^c) S with P^c the row-major factor read column-major.
-dctplus_status blaslt_apply(BlasLtPlan *b, int n, int64_t batch, int dir, const float *P, const float *S, float *D,
-                            hipStream_t s) {
-    auto &c = b->c[dir];
-    if (c.batch != batch) {
-        for (auto *l : {&c.a, &c.b, &c.d})
-            if (*l) {
-                hipblasLtMatrixLayoutDestroy(*l);
-                *l = nullptr;
+template <int BM, int BN, bool TRANSB>
+__global__ void __launch_bounds__(256) k_gemm32(const float *__restrict__ A, const float *__restrict__ P,
+                                                float *__restrict__ C, int64_t M, int n) {
+    constexpr int WM = BM / 2, WN = BN / 2;          // per-wave tile
+    constexpr int TM = WM / 16, TN = WN / 16;        // MFMA tiles per wave
+    constexpr int AV = BM * GKS / 4 / 256;           // float4 of A per thread and step
+    constexpr int BV = BN * GKS / 4 / 256;           // float4 of B per thread and step
+    static_assert(AV >= 1 && BV >= 1, "tile too small for 256 threads");
+    __shared__ __align__(16) float As[BM * GPAD];
+    __shared__ __align__(16) float Bs[BN * GPAD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l16 = lane & 15, g = lane >> 4;
+    const int64_t m0 = (int64_t)blockIdx.y * BM;
+    const int j0 = blockIdx.x * BN;
+    const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+    f4 acc[TM][TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    // operand registers of the next k-step
+    f4 ra[AV], rb[BV];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < AV; ++u) {
+            const int q = tid + 256 * u, r = q >> 2, c = q & 3;      // row r, float4 c of 4
+            const int64_t row = m0 + r;
+            ra[u] = row < M ? *reinterpret_cast<const f4 *>(A + row * n + k0 + 4 * c) : f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int u = 0; u < BV; ++u) {
+            const int q = tid + 256 * u;
+            if constexpr (TRANSB) {
+                const int r = q >> 2, c = q & 3;                      // output j0 + r, k0 + 4c ..
+                rb[u] = *reinterpret_cast<const f4 *>(P + (size_t)(j0 + r) * n + k0 + 4 * c);
+            } else {
+                const int kk = q / (BN / 4), c = q % (BN / 4);       // row k0 + kk, outputs j0 + 4c ..
+                rb[u] = *reinterpret_cast<const f4 *>(P + (size_t)(k0 + kk) * n + j0 + 4 * c);
             }
-        c.batch = -1;
-        bool ok = hipblasLtMatrixLayoutCreate(&c.a, HIP_R_32F, n, n, n) == HIPBLAS_STATUS_SUCCESS &&
-                  hipblasLtMatrixLayoutCreate(&c.b, HIP_R_32F, n, (uint64_t)batch, n) == HIPBLAS_STATUS_SUCCESS &&
-                  hipblasLtMatrixLayoutCreate(&c.d, HIP_R_32F, n, (uint64_t)batch, n) == HIPBLAS_STATUS_SUCCESS;
-        hipblasLtMatmulHeuristicResult_t res[1];
-        int found = 0;
-        ok = ok && hipblasLtMatmulAlgoGetHeuristic(b->h, b->desc[dir], c.a, c.b, c.d, c.d, b->pref, 1, res, &found) ==
-                       HIPBLAS_STATUS_SUCCESS &&
-             found > 0 && res[0].workspaceSize <= b->ws_bytes;
-        if (!ok) return fail(DCTPLUS_EDEVICE, "hipBLASLt has no algorithm for n = %d, batch = %lld", n, (long long)batch);
-        c.algo = res[0].algo;
-        c.batch = batch;
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int u = 0; u < AV; ++u) {
+            const int q = tid + 256 * u, r = q >> 2, c = q & 3;
+            *reinterpret_cast<f4 *>(As + r * GPAD + 4 * c) = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < BV; ++u) {
+            const int q = tid + 256 * u;
+            if constexpr (TRANSB) {
+                const int r = q >> 2, c = q & 3;
+                *reinterpret_cast<f4 *>(Bs + r * GPAD + 4 * c) = rb[u];
+            } else {
+                const int kk = q / (BN / 4), c = q % (BN / 4);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) Bs[(4 * c + e) * GPAD + kk] = rb[u][e];
+            }
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < n; k0 += GKS) {
+        __syncthreads();                       // the previous step's operands are consumed
+        stash();
+        __syncthreads();
+        if (k0 + GKS < n) fetch(k0 + GKS);     // in flight while this step is multiplied
+        f4 av[TM], bv[TN];
+#pragma unroll
+        for (int a = 0; a < TM; ++a) av[a] = *reinterpret_cast<const f4 *>(As + (wm + 16 * a + l16) * GPAD + 4 * g);
+#pragma unroll
+        for (int b = 0; b < TN; ++b) bv[b] = *reinterpret_cast<const f4 *>(Bs + (wn + 16 * b + l16) * GPAD + 4 * g);
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][s4], bv[b][s4], acc[a][b], 0, 0, 0);
     }
-    const float one = 1.0f, zero = 0.0f;
-    if (hipblasLtMatmul(b->h, b->desc[dir], &one, P, c.a, S, c.b, &zero, D, c.d, D, c.d, &c.algo, b->ws, b->ws_bytes,
-                        s) != HIPBLAS_STATUS_SUCCESS)
-        return fail(DCTPLUS_EDEVICE, "hipblasLtMatmul failed");
-    return DCTPLUS_OK;
+    // element v of lane (l16, g) is row 4 g + v (signal), column l16 (output)
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = m0 + wm + 16 * a + 4 * g + v;
+                if (row < M) C[row * n + j0 + wn + 16 * b + l16] = acc[a][b][v];
+            }
 }
 
 int num_cus() {
@@ -1045,6 +1056,21 @@ int factored_blocks(int64_t ntiles) {
     }
     const int64_t want = (ntiles + 3) / 4;
     return (int)(want < cap ? want : cap);
+}
+
+// The FP32 dense product for n > 64: 128 x 128 tiles when they give at least two
+// workgroups per CU, 64 x 64 otherwise (small batches).
+void launch_gemm32(const float *A, const float *P, float *C, int64_t M, int n, bool transb, hipStream_t s) {
+    const int64_t big = ((M + 127) / 128) * (n / 128);
+    if (n % 128 == 0 && big >= 2 * num_cus()) {
+        const dim3 grid((unsigned)(n / 128), (unsigned)((M + 127) / 128));
+        if (transb) hipLaunchKernelGGL((k_gemm32<128, 128, true>), grid, dim3(256), 0, s, A, P, C, M, n);
+        else hipLaunchKernelGGL((k_gemm32<128, 128, false>), grid, dim3(256), 0, s, A, P, C, M, n);
+    } else {
+        const dim3 grid((unsigned)(n / 64), (unsigned)((M + 63) / 64));
+        if (transb) hipLaunchKernelGGL((k_gemm32<64, 64, true>), grid, dim3(256), 0, s, A, P, C, M, n);
+        else hipLaunchKernelGGL((k_gemm32<64, 64, false>), grid, dim3(256), 0, s, A, P, C, M, n);
+    }
 }
 
 template <int N, bool BF>
@@ -1118,8 +1144,6 @@ dctplus_status stream_images(dctplus_plan_s *p, hipStream_t s) {
 }
 
 void dense_release(dctplus_plan_s *p) {
-    blaslt_release((BlasLtPlan *)p->blas);
-    p->blas = nullptr;
     if (p->simg) (void)hipFree(p->simg);
     p->simg = nullptr;
 }
@@ -1152,13 +1176,6 @@ dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s) {
         p->t.mt32 = nullptr;
         (void)hipGetLastError();
         return fail(DCTPLUS_ENOMEM, "hipMalloc for the %d x %d dense factor failed", n, n);
-    }
-    if (n > 64 && p->dtype == DCTPLUS_F32) {
-        // above n = 64 the FP32 dense product is a plain GEMM: the platform library runs it
-        BlasLtPlan *b = nullptr;
-        dctplus_status st = blaslt_create(n, &b);
-        if (st != DCTPLUS_OK) return st;
-        p->blas = b;
     }
     if (p->dtype == DCTPLUS_BF16) {
         e = hipMalloc(&p->t.mt16, sizeof(uint16_t) * elems);
@@ -1266,35 +1283,27 @@ dctplus_status dense_apply(dctplus_plan_s *p, const void *inv, void *outv, int64
         }
     } else {
         if (bf) return fail(DCTPLUS_EUNSUPPORTED, "BF16 dense route supports n <= 64");
+        if (batch > (int64_t)65535 * 64) return fail(DCTPLUS_EINVAL, "batch too large for the dense product");
         float *tmp = nullptr;
         if (pre) {
-            dctplus_status st = ensure_work(p, sizeof(float) * (size_t)batch * n);
+            dctplus_status st = stream_work(p, s, sizeof(float) * (size_t)batch * n, (void **)&tmp);
             if (st != DCTPLUS_OK) return st;
-            tmp = (float *)p->work;
         }
         const int nsig = n >= 4096 ? 1 : 4096 / n;
         const size_t lds = sizeof(cplx<float>) * (size_t)nsig * (n / 2);
         const dim3 dgrid((unsigned)((batch + nsig - 1) / nsig));
-        if (batch > INT32_MAX) return fail(DCTPLUS_EINVAL, "batch too large for the dense product");
-        BlasLtPlan *b = (BlasLtPlan *)p->blas;
-        if (!b) return fail(DCTPLUS_EDEVICE, "no GEMM set-up on this plan");
-        // row-major [batch, n] arrays are column-major n x batch with ld n; the
-        // row-major factor P (row i = output i) read column-major is P^T
-        dctplus_status st;
         if (!adjoint) {
             const float *A = in;
             if (pre) {
                 hipLaunchKernelGGL(k_dct_rows, dgrid, dim3(256), lds, s, p->t, in, tmp, batch, 0, nsig);
                 A = tmp;
             }
-            st = blaslt_apply(b, n, batch, 0, p->t.mt32, A, out, s);     // y_b = P x_b
+            launch_gemm32(A, p->t.mt32, out, batch, n, true, s);      // y_b = P x_b
         } else {
             float *C = pre ? tmp : out;
-            st = blaslt_apply(b, n, batch, 1, p->t.mt32, in, C, s);      // x_b = P^T y_b
-            if (st == DCTPLUS_OK && pre)
-                hipLaunchKernelGGL(k_dct_rows, dgrid, dim3(256), lds, s, p->t, tmp, out, batch, 1, nsig);
+            launch_gemm32(in, p->t.mt32, C, batch, n, false, s);      // x_b = P^T y_b
+            if (pre) hipLaunchKernelGGL(k_dct_rows, dgrid, dim3(256), lds, s, p->t, tmp, out, batch, 1, nsig);
         }
-        if (st != DCTPLUS_OK) return st;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "dense route launch");

@@ -479,9 +479,8 @@ dctplus_status fast_apply(dctplus_plan_s *p, const void *in, void *out, int64_t 
     double *scratch = nullptr;
     if (!c.big_in_lds) {
         const size_t bytes = sizeof(double) * big_doubles(n) * (size_t)c.nsig * blocks;
-        dctplus_status st = ensure_work(p, bytes);
+        dctplus_status st = stream_work(p, s, bytes, (void **)&scratch);
         if (st != DCTPLUS_OK) return st;
-        scratch = (double *)p->work;
     }
     if (blocks > 0x7fffffff) return fail(DCTPLUS_EINVAL, "batch too large");
     const dim3 grid((unsigned)blocks), block(c.threads);

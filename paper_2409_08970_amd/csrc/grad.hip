@@ -276,11 +276,12 @@ dctplus_status grad_apply(dctplus_plan_s *p, const float *y, const float *gy, in
     }
     if (!grho && !gv) return DCTPLUS_OK;
     const int nsplit = gram_splits(n, (size_t)256 << 20);
-    // the workspace may already hold a FAST/DENSE scratch from the gx call above,
-    // which has completed its use of it in stream order
-    st = ensure_work(p, (size_t)nsplit * n * n * sizeof(float) + grad_tail_bytes(n));
+    // the stream's workspace may already hold a FAST/DENSE scratch of the gx call above,
+    // which uses it earlier in the same stream's order
+    void *work = nullptr;
+    st = stream_work(p, s, (size_t)nsplit * n * n * sizeof(float) + grad_tail_bytes(n), &work);
     if (st != DCTPLUS_OK) return st;
-    return grad_launch(p, y, gy, batch, grho, gv, p->work, nsplit, s);
+    return grad_launch(p, y, gy, batch, grho, gv, work, nsplit, s);
 }
 
 dctplus_status grad_apply_static(dctplus_plan_s *p, const float *y, const float *gy, int64_t batch, float *gx,

@@ -457,6 +457,58 @@ def test_full_size_workload2_sampled(route):
     p.close()
 
 
+@pytest.mark.parametrize("n,batch,route", [(128, 70001, "dense"), (256, 33001, "dense"),
+                                           (256, 33001, "dense-factored"), (512, 301, "gft")])
+def test_dense_product_large_batches(n, batch, route):
+    """The FP32 dense product above n = 64 (our MFMA GEMM): batches that take its
+    128 x 128 tiles (at least two workgroups per CU) with a ragged last tile, and a
+    small batch on the 64 x 64 tiles; sampled rows against the oracle, every row in
+    the round trip."""
+    torch = _torch()
+    rho, v = case(n, "dense")
+    x = workloads.ar1(np.random.default_rng(n + batch), batch, n, 0.95)
+    fwd, adj = reference(n, rho, v)
+    p = make_plan(n, rho, v, route)
+    xt = torch.from_numpy(x).cuda()
+    y = p.forward(xt)
+    xr = p.adjoint(y)
+    torch.cuda.synchronize()
+    rows = np.unique(np.concatenate([np.random.default_rng(1).choice(batch, 300, replace=False),
+                                     np.arange(batch - 40, batch)]))
+    ri = torch.from_numpy(rows).cuda()
+    assert relerr(y[ri].cpu().double().numpy(), fwd(x[rows].astype(np.float64))) <= TOL32
+    assert relerr(xr.cpu().double().numpy(), x) <= 2 * TOL32
+    p.close()
+
+
+@pytest.mark.parametrize("route,n", [("fast", 8192), ("dense-factored", 256)])
+def test_two_streams_on_one_plan(route, n):
+    """Routes with scratch memory keep one workspace per stream: forward and adjoint
+    calls on two streams at once on one plan give the bits of the same calls made
+    one after the other on one stream."""
+    torch = _torch()
+    rho, v = case(n, "dense")
+    p = make_plan(n, rho, v, route)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    xa = torch.randn(64, n, device="cuda", generator=g)
+    xb = torch.randn(96, n, device="cuda", generator=g)
+    ya_ref, yb_ref = p.forward(xa), p.forward(xb)
+    ra_ref, rb_ref = p.adjoint(ya_ref), p.adjoint(yb_ref)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            ya = p.forward(xa, stream=s1)
+            ra = p.adjoint(ya, stream=s1)
+        with torch.cuda.stream(s2):
+            yb = p.forward(xb, stream=s2)
+            rb = p.adjoint(yb, stream=s2)
+        torch.cuda.synchronize()
+        assert torch.equal(ya, ya_ref) and torch.equal(yb, yb_ref)
+        assert torch.equal(ra, ra_ref) and torch.equal(rb, rb_ref)
+    p.close()
+
+
 def test_batch_edge_cases_and_errors():
     torch = _torch()
     from paper_2409_08970_amd import _binding as B

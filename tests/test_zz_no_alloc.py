@@ -92,8 +92,15 @@ def test_noalloc_grad_limits_are_refused_before_device_work():
     with pytest.raises(DctPlusError) as ei:
         dctplus_grad_noalloc(plan.handle, y.data_ptr(), gy.data_ptr(), 8, 0, grho.data_ptr(), 0)
     assert ei.value.status == 4            # EUNSUPPORTED: n above the scratch limit
+    plan.close()
+    # dl/dx on the factored dense form above n = 64 needs a workspace for the DCT pass
+    n = 256
+    v = workloads.unit_vector(workloads.rng(44), n)
+    plan = Plan(n, 0.5, v, route="dense", factored=True)
+    y = torch.zeros(8, n, device="cuda")
+    gy = torch.zeros_like(y)
     gx = torch.full_like(gy, 3.0)
-    with pytest.raises(DctPlusError) as ei:  # dl/dx on an FP32 dense plan above n = 64 needs the GEMM library
+    with pytest.raises(DctPlusError) as ei:
         dctplus_grad_noalloc(plan.handle, y.data_ptr(), gy.data_ptr(), 8, gx.data_ptr(), 0, 0)
     assert ei.value.status == 4
     torch.cuda.synchronize()
