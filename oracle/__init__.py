@@ -146,6 +146,51 @@ def basis(n: int, rho: float, v):
     return mu, fix_signs(X, rho, v)
 
 
+# --------------------------------------------------------------------------
+# Rank-k updates (Sec. 4.3, Cor. 4.5): L_k = L_path + sum_j rho_j v_j v_j^T.
+# --------------------------------------------------------------------------
+def laplacian_rank_k(n: int, rhos, vs) -> np.ndarray:
+    """L_path + sum_j rho_j v_j v_j^T, dense FP64 (Cor. 4.5's L_k)."""
+    L = laplacian(n, 0.0, np.zeros(n))
+    for rho, v in zip(rhos, vs):
+        v = np.asarray(v, dtype=np.float64)
+        L += float(rho) * np.outer(v, v)
+    return L
+
+
+def fix_signs_rank_k(X: np.ndarray, rhos, vs, tol: float = SIGN_DEFL_TOL) -> np.ndarray:
+    """Sign convention of a chain of rank-one updates (Cor. 4.5 applied one update at a
+    time, each stage with the rank-one convention): column i gets rho_j v_j^T x_i > 0 for
+    the last update j whose v_j is not orthogonal to x_i (an eigenvector orthogonal to
+    v_j is a deflated direction of stage j and keeps the sign it had before it); columns
+    orthogonal to every v_j get their largest |U^T x_i| entry positive."""
+    n = X.shape[0]
+    X = X.copy()
+    U = None
+    for i in range(n):
+        for rho, v in reversed(list(zip(rhos, vs))):
+            v = np.asarray(v, dtype=np.float64)
+            t = float(v @ X[:, i])
+            if rho != 0.0 and abs(t) > tol * max(np.linalg.norm(v), 1e-300):
+                if rho * t < 0:
+                    X[:, i] = -X[:, i]
+                break
+        else:
+            if U is None:
+                U = dct2_matrix(n)
+            c = U.T @ X[:, i]
+            if c[np.argmax(np.abs(c))] < 0:
+                X[:, i] = -X[:, i]
+    return X
+
+
+def basis_rank_k(n: int, rhos, vs):
+    """(mu, X) of L_path + sum_j rho_j v_j v_j^T: Jacobi on the assembled matrix, eigenvalues
+    ascending, signs by ``fix_signs_rank_k``."""
+    mu, X = eigh_jacobi(laplacian_rank_k(n, rhos, vs))
+    return mu, fix_signs_rank_k(X, rhos, vs)
+
+
 def forward(X: np.ndarray, x) -> np.ndarray:
     """y = X^T x for every row x of a [batch, n] array (FP64)."""
     x = np.ascontiguousarray(x, dtype=np.float64)

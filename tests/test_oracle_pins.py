@@ -488,3 +488,117 @@ def test_pins_catch_mutants(mutant):
     caught = (pin_rho_zero(fn, 8) > 1e-6) or (pin_self_loop(fn, 8) > 1e6) \
         or (pin_self_loop(fn, 8, True) > 1e6)
     assert caught
+
+
+# --------------------------------------------------------------------------
+# rank-k updates (Sec. 4.3, Cor. 4.5)
+# --------------------------------------------------------------------------
+def _edges_case(n, seed, count):
+    """`count` seeded added edges (random i != j, weights in [0.5, 2]) as rank-one updates
+    (rho = 2 w, v = (e_i - e_j)/sqrt 2) and as an edge list."""
+    g = np.random.default_rng(seed)
+    rhos, vs, edges = [], [], []
+    for _ in range(count):
+        i, j = sorted(int(t) for t in g.choice(n, 2, replace=False))
+        w = float(g.uniform(0.5, 2.0))
+        rho, v = oracle.candidate_update(n, 1, i, j, w)
+        rhos.append(rho)
+        vs.append(v)
+        edges.append((i, j, w))
+    return rhos, vs, edges
+
+
+def _chain_basis(n, rhos, vs, z_from_base=False):
+    """X_k built stage by stage as Cor. 4.5 states it, X_j = X_{j-1} diag(z_j)
+    C(mu_{j-1}, mu_j) diag(a_j), with a_j > 0 in the forward orientation
+    (X_j^T = diag(a_j) C(mu_j, mu_{j-1}) diag(z_j) X_{j-1}^T).  The eigenvalues mu_j of each
+    stage are taken from Jacobi on the stage's assembled matrix (so this checks the
+    eigenvector structure only), z_j = X_{j-1}^T v_j (or U^T v_j with z_from_base, the
+    printed form of the corollary).  Directions with z_j,m = 0 (every added edge keeps the
+    constant vector) are deflated: the stage keeps x_m with eigenvalue mu_{j-1,m}.  Stages
+    must have simple spectra."""
+    X = oracle.dct2_matrix(n)
+    d = oracle.path_eigenvalues(n)
+    for k in range(len(rhos)):
+        v = np.asarray(vs[k], dtype=np.float64)
+        z = (oracle.dct2_matrix(n).T @ v) if z_from_base else (X.T @ v)
+        live = np.abs(z) > 1e-12 * np.linalg.norm(z)
+        mu, _ = oracle.eigh_jacobi(oracle.laplacian_rank_k(n, rhos[:k + 1], vs[:k + 1]))
+        Wt = np.zeros((n, n))
+        used = set()
+        for i in range(n):
+            hit = [m for m in np.nonzero(~live)[0] if abs(d[m] - mu[i]) < 1e-9 and m not in used]
+            if hit:
+                Wt[i, hit[0]] = 1.0                            # deflated: x_m itself
+                used.add(hit[0])
+                continue
+            w = z[live] / (mu[i] - d[live])                    # row of C(mu_j, mu_{j-1}) diag(z)
+            Wt[i, live] = w / np.linalg.norm(w)                # times a_i > 0
+        X = X @ Wt.T
+        d = mu
+    return d, X
+
+
+@pytest.mark.parametrize("n", [8, 16, 64])
+def test_rank_k_laplacian_is_the_graph_laplacian(n):
+    rhos, vs, edges = _edges_case(n, 100 + n, 3)
+    L = oracle.laplacian_rank_k(n, rhos, vs)
+    assert np.abs(L - graph_laplacian(n, edges=edges)).max() < 1e-14
+    # a self-loop and an edge together
+    r1, v1 = oracle.candidate_update(n, 0, n - 1, n - 1, 0.8)
+    r2, v2 = oracle.candidate_update(n, 1, 1, n - 2, 1.3)
+    L = oracle.laplacian_rank_k(n, [r1, r2], [v1, v2])
+    assert np.abs(L - graph_laplacian(n, edges=[(1, n - 2, 1.3)], loops=[(n - 1, 0.8)])).max() < 1e-14
+
+
+@pytest.mark.parametrize("n", [8, 32, 64])
+def test_rank_k_basis_diagonalises_and_signs(n):
+    rhos, vs, _ = _edges_case(n, 200 + n, 3)
+    mu, X = oracle.basis_rank_k(n, rhos, vs)
+    L = oracle.laplacian_rank_k(n, rhos, vs)
+    assert np.all(np.diff(mu) > 0)
+    assert np.abs(X.T @ X - np.eye(n)).max() < 1e-12
+    assert np.abs(X @ np.diag(mu) @ X.T - L).max() < 1e-12
+    # the last update sees every eigenvector it is not orthogonal to with a positive sign
+    t = rhos[-1] * (vs[-1] @ X)
+    assert np.all((t > 0) | (np.abs(t) < 1e-9))
+
+
+@pytest.mark.parametrize("n", [8, 64])
+def test_rank_k_reduces_to_rank_one(n):
+    g = np.random.default_rng(7 + n)
+    v = workloads.unit_vector(g, n)
+    mu1, X1 = oracle.basis(n, 0.9, v)
+    muk, Xk = oracle.basis_rank_k(n, [0.9], [v])
+    assert np.abs(mu1 - muk).max() < 1e-13 and np.abs(X1 - Xk).max() < 1e-12
+    # one update split into two halves along the same v: the same L, the same signs
+    mu2, X2 = oracle.basis_rank_k(n, [0.45, 0.45], [v, v])
+    assert np.abs(mu1 - mu2).max() < 1e-12 and np.abs(X1 - X2).max() < 1e-10
+
+
+@pytest.mark.parametrize("n", [16, 64])
+def test_rank_k_order_of_updates(n):
+    rhos, vs, _ = _edges_case(n, 300 + n, 2)
+    mu_a, X_a = oracle.basis_rank_k(n, rhos, vs)
+    mu_b, X_b = oracle.basis_rank_k(n, rhos[::-1], vs[::-1])
+    assert np.abs(mu_a - mu_b).max() < 1e-12
+    assert np.abs(np.abs(X_a) - np.abs(X_b)).max() < 1e-10
+
+
+@pytest.mark.parametrize("n", [8, 16, 32])
+def test_rank_k_chain_of_cauchy_factors(n):
+    """Cor. 4.5 with z_k = X_{k-1}^T v_k reproduces the Jacobi basis of L_k column by
+    column (values and the chain's sign convention); with z_k = U^T v_k, as printed, it
+    does not (the corollary's induction needs the previous stage's basis)."""
+    for seed in range(3):
+        rhos, vs, _ = _edges_case(n, 400 + 10 * n + seed, 3)
+        mu, X = oracle.basis_rank_k(n, rhos, vs)
+        gaps = min(np.diff(oracle.eigh_jacobi(oracle.laplacian_rank_k(n, rhos[:j + 1], vs[:j + 1]))[0]).min()
+                   for j in range(3))
+        if gaps < 1e-6:
+            continue
+        d, Xc = _chain_basis(n, rhos, vs)
+        assert np.abs(d - mu).max() < 1e-12
+        assert np.abs(Xc - X).max() < 1e-9, np.abs(Xc - X).max()
+        _, Xw = _chain_basis(n, rhos, vs, z_from_base=True)
+        assert not (np.abs(np.abs(Xw) - np.abs(X)).max() <= 1e-3)     # NaN or far off
