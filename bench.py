@@ -376,6 +376,26 @@ def main():
             comp[f"n{nl}_workload"] = large
             del A, At, x3, y3, r3
             torch.cuda.empty_cache()
+        # rank-k updates (Cor. 4.5): three added edges (weights in [0.5, 2]) on the workload-2
+        # batch; the composite Cauchy factor goes through the same factored kernel
+        import oracle
+        g3 = np.random.default_rng(4242)
+        rk_rhos, rk_V = [], []
+        for _ in range(3):
+            i3, j3 = sorted(int(t) for t in g3.choice(n, 2, replace=False))
+            r3, v3 = oracle.candidate_update(n, 1, i3, j3, float(g3.uniform(0.5, 2.0)))
+            rk_rhos.append(r3)
+            rk_V.append(v3)
+        torch.cuda.synchronize()
+        t_plan = time.perf_counter()
+        pk = Plan(n, rk_rhos, rk_V, route="dense", dtype="f32split", factored=True)
+        torch.cuda.synchronize()
+        plan_ms = (time.perf_counter() - t_plan) * 1e3
+        tk = time_pair(torch, lambda: pk.forward(x, out=y), lambda: pk.adjoint(y, out=xr), args.steps, args.warmup)
+        pk.close()
+        comp["rank3_edges_n64"] = {"ms_per_step": tk[0], "value": batch * n / (tk[0] * 1e-3),
+                                   "median_launch_ms": 0.5 * (tk[3] + tk[4]), "plan_ms_host": plan_ms,
+                                   "updates": "3 added edges, weights U[0.5, 2]; DENSE factored split-BF16"}
         result["comparators"] = comp
         for k, v in comp.items():
             print(k, v, file=sys.stderr, flush=True)

@@ -120,6 +120,32 @@ void dctplus_default_opts(dctplus_opts *opts);
 dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const dctplus_opts *opts,
                             void *stream, dctplus_plan_t *out);
 
+/*
+ * Build a plan for k rank-one updates, L = L_path + sum_{j<k} rho_j v_j v_j^T (Sec. 4.3,
+ * Cor. 4.5: rank-k updates keep the Cauchy structure, by induction over the updates).
+ *   k       : 1 <= k <= 64; k = 1 is dctplus_plan.
+ *   rho_host: HOST array of k finite doubles; V_host: HOST k x n doubles, row j = v_j
+ *             (both copied).
+ * Update j >= 2 is a rank-one update of diag(mu_{j-1}) with z_j = X_{j-1}^T v_j (the basis
+ * of the updates before it; the corollary's induction needs it):
+ *     X_j^T = diag(a_j) C(mu_j, mu_{j-1}) diag(z_j) X_{j-1}^T,
+ * with the rank-one conventions per update (a_j > 0, deflation of z_j,m = 0 keeping row m,
+ * ascending rows, a root tying a deflated eigenvalue ordered after it).  The set-up runs
+ * in FP64 on the GPU and composes the updates' Cauchy factors into one n x n factor C_k
+ * (X_k^T = C_k U^T), which the DENSE route applies after the DCT-II (factored) or folds
+ * with it; GFT applies X_k^T.  Resulting sign convention: eigenvector x_i has
+ * rho_j v_j^T x_i > 0 for the last update j with v_j^T x_i != 0.
+ * Limits for k > 1: DENSE and GFT routes only (AUTO = DENSE; FAST is EUNSUPPORTED: the
+ * later poles are not Chebyshev nodes), n <= 4096 (EUNSUPPORTED above).
+ * Errors: as dctplus_plan, plus EDEGENERATE when an update meets two equal eigenvalues of
+ * the updates before it and touches both (the stage would first need a rotation inside
+ * that eigenspace).  dctplus_grad on such a plan gives dl/dx only (grho / gv requested:
+ * EUNSUPPORTED).  Forward, adjoint, plan_info (the last update's tables) and destroy as
+ * for rank-one plans.
+ */
+dctplus_status dctplus_plan_rank_k(int64_t n, int32_t k, const double *rho_host, const double *V_host,
+                                   const dctplus_opts *opts, void *stream, dctplus_plan_t *out);
+
 /* y = X^T x for `batch` signals (Thm 3.1; Alg. 1 on the FAST route).
  * x, y: device arrays [batch, n] of the plan's element type; x and y must not alias.
  * batch == 0 is a no-op; batch < 0 is EINVAL. */

@@ -19,14 +19,14 @@ import ctypes
 
 from . import _binding as B
 from ._binding import (DctPlusError, dctplus_adjoint, dctplus_default_opts, dctplus_forward, dctplus_grad,
-                       dctplus_grad_noalloc,
+                       dctplus_grad_noalloc, dctplus_plan_rank_k,
                        dctplus_last_error, dctplus_plan, dctplus_plan_destroy, dctplus_plan_info,
                        dctplus_plan_table, dctplus_select, dctplus_select_destroy, dctplus_select_factor,
                        dctplus_select_plan, dctplus_select_size, dctplus_select_tune, dctplus_status_string)
 
 __all__ = [
     "Plan", "DctPlusFn", "dctplus", "DctPlusError", "dctplus_plan", "dctplus_forward", "dctplus_adjoint",
-    "dctplus_grad", "dctplus_grad_noalloc", "dctplus_plan_info", "dctplus_plan_table", "dctplus_plan_destroy", "dctplus_status_string",
+    "dctplus_grad", "dctplus_grad_noalloc", "dctplus_plan_rank_k", "dctplus_plan_info", "dctplus_plan_table", "dctplus_plan_destroy", "dctplus_status_string",
     "dctplus_last_error", "dctplus_default_opts", "SelectPlan", "dctplus_select_plan", "dctplus_select",
     "dctplus_select_factor", "dctplus_select_size", "dctplus_select_destroy", "dctplus_select_tune",
 ]
@@ -44,9 +44,12 @@ def _stream(stream=None) -> int:
 
 
 class Plan:
-    """Owns one dctplus plan (device tables built on the GPU in FP64)."""
+    """Owns one dctplus plan (device tables built on the GPU in FP64).
 
-    def __init__(self, n: int, rho: float, v, route: str = "auto", dtype: str = "f32",
+    rho, v: one rank-one update (a float and n values), or k updates for a rank-k plan
+    (k floats and a k x n array, row j = v_j; Cor. 4.5)."""
+
+    def __init__(self, n: int, rho, v, route: str = "auto", dtype: str = "f32",
                  nufft_width: int = 0, direct_kappa: float = 0.0, defl_tol: float = 0.0, device: int = -1,
                  stream=None, factored: bool = False):
         import numpy as np
@@ -65,13 +68,20 @@ class Plan:
         o.device = device
         o.factored = 1 if factored else 0
         self.n = int(n)
-        self.rho = float(rho)
-        self.v = np.asarray(v, dtype=np.float64).reshape(-1).copy()
+        rhos = np.atleast_1d(np.asarray(rho, dtype=np.float64))
+        self.k = int(rhos.size)
+        self.rho = float(rhos[0]) if self.k == 1 else rhos.copy()
+        self.v = np.asarray(v, dtype=np.float64).reshape(self.k, -1).copy()
+        if self.k == 1:
+            self.v = self.v.reshape(-1)
         self.dtype = dtype
         self.device = device
         self._h = None
         with torch.cuda.device(device):
-            _, self._h = B.dctplus_plan(self.n, self.rho, self.v, o, _stream(stream))
+            if self.k == 1:
+                _, self._h = B.dctplus_plan(self.n, self.rho, self.v, o, _stream(stream))
+            else:
+                _, self._h = B.dctplus_plan_rank_k(self.n, rhos, self.v, o, _stream(stream))
         info = B.dctplus_plan_info(self._h, self.n)
         self.route = ROUTE_NAMES[int(info["counts"][3])]
         self.info = info

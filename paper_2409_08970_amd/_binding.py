@@ -31,6 +31,7 @@ EXPORTED = (
     "dctplus_plan_info", "dctplus_plan_table", "dctplus_plan_destroy", "dctplus_status_string",
     "dctplus_last_error", "dctplus_select_plan", "dctplus_select", "dctplus_select_factor",
     "dctplus_select_size", "dctplus_select_destroy", "dctplus_select_tune", "dctplus_grad_noalloc",
+    "dctplus_plan_rank_k",
 )
 
 
@@ -71,6 +72,9 @@ def load(path: str = LIB_PATH):
     lib.dctplus_plan.argtypes = [i64, ctypes.c_double, dp, ctypes.POINTER(dctplus_opts), vp,
                                  ctypes.POINTER(vp)]
     lib.dctplus_plan.restype = ctypes.c_int
+    lib.dctplus_plan_rank_k.argtypes = [i64, ctypes.c_int32, dp, dp, ctypes.POINTER(dctplus_opts), vp,
+                                        ctypes.POINTER(vp)]
+    lib.dctplus_plan_rank_k.restype = ctypes.c_int
     lib.dctplus_forward.argtypes = [vp, vp, vp, i64, vp]
     lib.dctplus_forward.restype = ctypes.c_int
     lib.dctplus_adjoint.argtypes = [vp, vp, vp, i64, vp]
@@ -130,6 +134,22 @@ def dctplus_plan(n: int, rho: float, v, opts: dctplus_opts | None = None, stream
                              ctypes.byref(handle))
     if check:
         _check(st, "dctplus_plan")
+    return st, handle
+
+
+def dctplus_plan_rank_k(n: int, rhos, V, opts: dctplus_opts | None = None, stream: int = 0,
+                        check: bool = True):
+    """Returns (status, handle).  rhos: k floats; V: k x n (row j = v_j), copied."""
+    import numpy as np
+    r = np.ascontiguousarray(np.asarray(rhos, dtype=np.float64).reshape(-1))
+    Varr = np.ascontiguousarray(np.asarray(V, dtype=np.float64).reshape(-1))   # k x n, row-major
+    handle = ctypes.c_void_p()
+    dp = ctypes.POINTER(ctypes.c_double)
+    st = load().dctplus_plan_rank_k(int(n), int(r.size), r.ctypes.data_as(dp), Varr.ctypes.data_as(dp),
+                                    ctypes.byref(opts) if opts is not None else None, ctypes.c_void_p(stream),
+                                    ctypes.byref(handle))
+    if check:
+        _check(st, "dctplus_plan_rank_k")
     return st, handle
 
 

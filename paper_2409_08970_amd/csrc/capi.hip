@@ -147,18 +147,28 @@ void dctplus_default_opts(dctplus_opts *o) {
     o->factored = 0;
 }
 
-dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const dctplus_opts *opts, void *stream,
-                            dctplus_plan_t *out) {
+// Plans of dctplus_plan (k = 1) and dctplus_plan_rank_k: rho[k], V[k * n] on the host.
+static dctplus_status plan_create(int64_t n, int32_t k, const double *rhos, const double *V, const dctplus_opts *opts,
+                                  void *stream, dctplus_plan_t *out) {
     if (!out) return fail(DCTPLUS_EINVAL, "null output pointer");
     *out = nullptr;
     if (n < 2) return fail(DCTPLUS_EINVAL, "n = %lld < 2", (long long)n);
+    if (k < 1 || k > kMaxRank) return fail(DCTPLUS_EINVAL, "k = %d: 1 <= k <= %d updates", (int)k, kMaxRank);
     if (n < 4 || n > 16384 || (n & (n - 1)))
         return fail(DCTPLUS_EUNSUPPORTED, "n = %lld: supported sizes are powers of two in [4, 16384]",
                     (long long)n);
-    if (!isfinite(rho)) return fail(DCTPLUS_EINVAL, "rho is not finite");
-    if (!v_host) return fail(DCTPLUS_EINVAL, "null v");
-    for (int64_t i = 0; i < n; ++i)
-        if (!isfinite(v_host[i])) return fail(DCTPLUS_EINVAL, "v[%lld] is not finite", (long long)i);
+    if (k > 1 && n > 4096)
+        return fail(DCTPLUS_EUNSUPPORTED, "rank-k plans support n <= 4096 (dense n x n FP64 set-up)");
+    if (!rhos) return fail(DCTPLUS_EINVAL, "null rho");
+    if (!V) return fail(DCTPLUS_EINVAL, "null v");
+    for (int j = 0; j < k; ++j) {
+        if (!isfinite(rhos[j])) return fail(DCTPLUS_EINVAL, "rho[%d] is not finite", j);
+        for (int64_t i = 0; i < n; ++i)
+            if (!isfinite(V[(size_t)j * n + i]))
+                return fail(DCTPLUS_EINVAL, "v[%d][%lld] is not finite", j, (long long)i);
+    }
+    const double rho = rhos[0];
+    const double *v_host = V;
     dctplus_opts o;
     dctplus_default_opts(&o);
     if (opts) o = *opts;
@@ -174,6 +184,12 @@ dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const d
     if (o.nufft_width < 4 || o.nufft_width > kMaxWidth || (o.nufft_width & 1))
         return fail(DCTPLUS_EINVAL, "nufft_width %d: must be even, 4..%d", o.nufft_width, kMaxWidth);
     int route = o.route;
+    if (k > 1) {
+        // later updates have non-Chebyshev poles: the composite factor is applied densely
+        if (route == DCTPLUS_ROUTE_FAST)
+            return fail(DCTPLUS_EUNSUPPORTED, "rank-k plans (k > 1) use the DENSE and GFT routes");
+        if (route == DCTPLUS_ROUTE_AUTO) route = DCTPLUS_ROUTE_DENSE;
+    }
     if (route == DCTPLUS_ROUTE_AUTO) {
         // measured on MI355X (forward + adjoint, FP32): the O(n^2) MFMA/GEMM product wins up
         // to n = 1024, the O(n log n) route from n = 4096 on.  FP64 plans stay on the dense
@@ -215,13 +231,26 @@ dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const d
     p->direct_kappa = o.direct_kappa;
     p->width = o.nufft_width;
     p->factored = o.factored;
+    p->rank = k;
+    p->defer_dense = (k > 1);
     dctplus_status st = plan_build(p, v_host, (hipStream_t)stream);
+    if (st == DCTPLUS_OK && k > 1) st = rank_k_build(p, k, rhos, V, (hipStream_t)stream);
     if (st != DCTPLUS_OK) {
         dctplus_plan_destroy(p);
         return st;
     }
     *out = p;
     return DCTPLUS_OK;
+}
+
+dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const dctplus_opts *opts, void *stream,
+                            dctplus_plan_t *out) {
+    return plan_create(n, 1, &rho, v_host, opts, stream, out);
+}
+
+dctplus_status dctplus_plan_rank_k(int64_t n, int32_t k, const double *rho_host, const double *V_host,
+                                   const dctplus_opts *opts, void *stream, dctplus_plan_t *out) {
+    return plan_create(n, k, rho_host, V_host, opts, stream, out);
 }
 
 dctplus_status dctplus_forward(dctplus_plan_t p, const void *x, void *y, int64_t batch, void *stream) {
@@ -243,6 +272,8 @@ dctplus_status dctplus_adjoint(dctplus_plan_t p, const void *y, void *x, int64_t
 dctplus_status dctplus_grad(dctplus_plan_t p, const void *y, const void *gy, int64_t batch, void *gx, double *grho,
                             double *gv, void *stream) {
     if (!p) return fail(DCTPLUS_EINVAL, "null plan");
+    if (p->rank > 1 && (grho || gv))
+        return fail(DCTPLUS_EUNSUPPORTED, "d/drho and d/dv are implemented for rank-one plans");
     if (p->dtype != DCTPLUS_F32 && p->dtype != DCTPLUS_F32_SPLIT)
         return fail(DCTPLUS_EUNSUPPORTED, "gradients are implemented for FP32 plans");
     if (batch < 0) return fail(DCTPLUS_EINVAL, "batch = %lld < 0", (long long)batch);
@@ -262,6 +293,8 @@ dctplus_status dctplus_grad(dctplus_plan_t p, const void *y, const void *gy, int
 dctplus_status dctplus_grad_noalloc(dctplus_plan_t p, const void *y, const void *gy, int64_t batch, void *gx,
                                     double *grho, double *gv, void *stream) {
     if (!p) return fail(DCTPLUS_EINVAL, "null plan");
+    if (p->rank > 1 && (grho || gv))
+        return fail(DCTPLUS_EUNSUPPORTED, "d/drho and d/dv are implemented for rank-one plans");
     if (p->dtype != DCTPLUS_F32 && p->dtype != DCTPLUS_F32_SPLIT)
         return fail(DCTPLUS_EUNSUPPORTED, "gradients are implemented for FP32 plans");
     if (batch < 0) return fail(DCTPLUS_EINVAL, "batch = %lld < 0", (long long)batch);

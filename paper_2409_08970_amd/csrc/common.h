@@ -15,6 +15,7 @@ constexpr int kMaxLogN = 14;            // n <= 16384
 constexpr int kMaxDirect = 512;         // rows summed exactly on the FAST route
 constexpr int kMaxWidth = 16;           // NUFFT window taps
 constexpr int kTaps = kMaxWidth + 2;    // stride of the aligned window table (taps past width + 2 are 0)
+constexpr int kMaxRank = 64;            // rank-one updates of a rank-k plan
 
 template <typename T>
 struct cplx {
@@ -73,6 +74,8 @@ struct dctplus_plan_s {
     double defl_tol, direct_kappa;
     int width;
     int factored;             // DENSE route keeps the DCT and the Cauchy factor apart
+    int defer_dense;          // plan_build leaves the dense operands to the caller (rank-k plans)
+    int rank;                 // number of rank-one updates (1 for dctplus_plan)
     void *dev_mem;            // one allocation holding every table
     size_t dev_bytes;
     // workspaces (FAST-route scratch for large n, the factored route's DCT output above
@@ -101,6 +104,14 @@ dctplus_status fast_apply(dctplus_plan_s *p, const void *in, void *out, int64_t 
 dctplus_status dense_apply(dctplus_plan_s *p, const void *in, void *out, int64_t batch, bool adjoint,
                            hipStream_t s);
 dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s);
+// dense operands from a given FP64 Cauchy factor (row-major n x n) instead of the plan's
+dctplus_status dense_build_from(dctplus_plan_s *p, const double *src, hipStream_t s);
+// M = diag(a) C(mu, lambda) diag(z) of a rank-one plan, FP64 row-major n x n
+void launch_cauchy_f64(const dctplus_plan_s *p, double *M, hipStream_t s);
+// FP64 C = A B(k, j) on MFMA: B(k, j) = P[j][k] (transb) or P[k][j]; A is [batch x n]
+void gemm64(const double *A, const double *P, double *C, int64_t batch, int n, bool transb, hipStream_t s);
+// the chain of Cor. 4.5 for updates 2..k (rankk.hip), after plan_build of update 1
+dctplus_status rank_k_build(dctplus_plan_s *p, int k, const double *rho_host, const double *V_host, hipStream_t s);
 void dense_release(dctplus_plan_s *p);
 dctplus_status grad_apply(dctplus_plan_s *p, const float *y, const float *gy, int64_t batch, float *gx,
                           double *grho, double *gv, hipStream_t s);

@@ -44,14 +44,18 @@ __device__ __forceinline__ __bf16 bits2bf(uint16_t b) {
 // One workgroup per row.  Row entries a z_j / (mu - lambda_j) (deflated rows:
 // e_o) are computed where they are needed; LDS holds only the n/2 complex
 // doubles of the FFT (gft) or the n doubles of the row (M itself).
+// With `src` (row-major n x n FP64) the row entries are read from it instead (a
+// composite Cauchy factor of a rank-k plan).
 __global__ void __launch_bounds__(256) k_dense_rows(PlanTables t, int gft, float *__restrict__ P32,
-                                                    uint16_t *__restrict__ P16, double *__restrict__ P64) {
+                                                    uint16_t *__restrict__ P16, double *__restrict__ P64,
+                                                    const double *__restrict__ src) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = t.n, logn = t.logn, i = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
     const int kind = t.kind[i];
     const int o = t.origin[i];
     const double tau = t.tau[i], a = t.a[i];
     auto entry = [&](int j) -> double {
+        if (src) return src[(size_t)i * n + j];
         if (kind == ROW_DEFLATED) return (j == o) ? 1.0 : 0.0;
         const double zj = t.z[j];
         if (zj == 0.0) return 0.0;
@@ -1148,7 +1152,7 @@ void dense_release(dctplus_plan_s *p) {
     p->simg = nullptr;
 }
 
-dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s) {
+dctplus_status dense_build_from(dctplus_plan_s *p, const double *src, hipStream_t s) {
     const int n = (int)p->n;
     const size_t elems = (size_t)n * n;
     hipError_t e;
@@ -1166,7 +1170,7 @@ dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s) {
                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
             return hip_fail(e, "dense factor build (LDS size)");
         hipLaunchKernelGGL(k_dense_rows, dim3(n), dim3(256), lds, s, p->t, 1, (float *)nullptr,
-                           (uint16_t *)nullptr, p->t.mt64);
+                           (uint16_t *)nullptr, p->t.mt64, src);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "dense factor build");
         return DCTPLUS_OK;
@@ -1194,10 +1198,22 @@ dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s) {
                                                 (int)lds)) != hipSuccess)
         return hip_fail(e, "dense factor build (LDS size)");
     hipLaunchKernelGGL(k_dense_rows, dim3(n), dim3(256), lds, s, p->t, gft, p->t.mt32, p->t.mt16,
-                       (double *)nullptr);
+                       (double *)nullptr, src);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "dense factor build");
     return stream_images(p, s);
+}
+
+dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s) { return dense_build_from(p, nullptr, s); }
+
+void launch_cauchy_f64(const dctplus_plan_s *p, double *M, hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_rows, dim3((unsigned)p->n), dim3(256), 0, s, p->t, 0, (float *)nullptr,
+                       (uint16_t *)nullptr, M, (const double *)nullptr);
+}
+
+void gemm64(const double *A, const double *P, double *C, int64_t batch, int n, bool transb, hipStream_t s) {
+    const dim3 grid((unsigned)((n + TBN - 1) / TBN), (unsigned)((batch + TBM - 1) / TBM));
+    hipLaunchKernelGGL(k_gemm64, grid, dim3(256), 0, s, A, P, C, batch, n, transb ? 1 : 0);
 }
 
 dctplus_status dense_apply(dctplus_plan_s *p, const void *inv, void *outv, int64_t batch, bool adjoint,

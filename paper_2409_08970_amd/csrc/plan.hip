@@ -518,7 +518,7 @@ dctplus_status plan_build(dctplus_plan_s *p, const double *v_host, hipStream_t s
         hipLaunchKernelGGL(k_direct, dim3(t.ndirect), dim3(256), 0, s, t);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "direct rows");
     }
-    if (p->route == DCTPLUS_ROUTE_DENSE || p->route == DCTPLUS_ROUTE_GFT) {
+    if ((p->route == DCTPLUS_ROUTE_DENSE || p->route == DCTPLUS_ROUTE_GFT) && !p->defer_dense) {
         dctplus_status ds = dense_build(p, s);
         if (ds != DCTPLUS_OK) return ds;
     }

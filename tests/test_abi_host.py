@@ -148,3 +148,20 @@ def test_select_calls_on_null_plan_are_rejected(lib):
     assert lib.dctplus_select_size(None) == -1
     assert lib.dctplus_select_plan(1, 2, 64, None, None, None, ctypes.byref(ctypes.c_void_p())) == 1
     lib.dctplus_select_destroy(None)
+
+
+def test_rank_k_plan_rejects_bad_arguments_on_host(lib):
+    from paper_2409_08970_amd import _binding as B
+    n = 64
+    V = np.ones((2, n)) / 8.0
+    assert B.dctplus_plan_rank_k(n, [], np.zeros((0, n)), check=False)[0] == B.DCTPLUS_EINVAL        # k = 0
+    assert B.dctplus_plan_rank_k(n, np.ones(65), np.ones((65, n)), check=False)[0] == B.DCTPLUS_EINVAL
+    bad = V.copy()
+    bad[1, 3] = np.nan
+    assert B.dctplus_plan_rank_k(n, [1.0, 1.0], bad, check=False)[0] == B.DCTPLUS_EINVAL
+    assert B.dctplus_plan_rank_k(n, [1.0, np.inf], V, check=False)[0] == B.DCTPLUS_EINVAL
+    assert B.dctplus_plan_rank_k(8192, [1.0, 1.0], np.ones((2, 8192)), check=False)[0] == B.DCTPLUS_EUNSUPPORTED
+    o = B.dctplus_default_opts()
+    o.route = B.DCTPLUS_ROUTE_FAST
+    assert B.dctplus_plan_rank_k(n, [1.0, 1.0], V, o, check=False)[0] == B.DCTPLUS_EUNSUPPORTED
+    assert lib.dctplus_plan_rank_k(n, 2, None, None, None, None, None) == B.DCTPLUS_EINVAL
