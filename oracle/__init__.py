@@ -119,14 +119,15 @@ def dct2_matrix(n: int) -> np.ndarray:
     return U
 
 
-def fix_signs(X: np.ndarray, rho: float, v, tol: float = SIGN_DEFL_TOL) -> np.ndarray:
-    """Apply the sign convention to the eigenvector columns of X (copy)."""
+def fix_signs(X: np.ndarray, rho: float, v, tol: float = SIGN_DEFL_TOL, base=None) -> np.ndarray:
+    """Apply the sign convention to the eigenvector columns of X (copy).  base: the
+    unperturbed basis (columns) for the deflated rows' rule, the DCT-II by default."""
     n = X.shape[0]
     v = np.asarray(v, dtype=np.float64)
     X = X.copy()
     vx = v @ X
     scale = tol * max(np.linalg.norm(v), 1e-300)
-    U = None
+    U = base
     for i in range(n):
         if rho != 0.0 and abs(vx[i]) > scale:
             if rho * vx[i] < 0:
@@ -144,6 +145,33 @@ def basis(n: int, rho: float, v):
     """(mu, X): eigenvalues ascending and signed eigenvectors (columns) of L_path + rho v v^T."""
     mu, X = eigh_jacobi(laplacian(n, rho, v))
     return mu, fix_signs(X, rho, v)
+
+
+# --------------------------------------------------------------------------
+# A rank-one update of a general base (Thm 3.1 for any symmetric base; Thm 3.2).
+# --------------------------------------------------------------------------
+def basis_general(lam, U, rho: float, v):
+    """(mu, X) of U diag(lam) U^T + rho v v^T: Jacobi on the assembled matrix, eigenvalues
+    ascending; signs rho v^T x_i > 0, and for rows orthogonal to v the largest |U^T x_i|
+    entry positive (the base's own vectors, as the DCT-II is for the path)."""
+    U = np.asarray(U, dtype=np.float64)
+    lam = np.asarray(lam, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    L = (U * lam[None, :]) @ U.T + float(rho) * np.outer(v, v)
+    L = 0.5 * (L + L.T)
+    mu, X = eigh_jacobi(L)
+    return mu, fix_signs(X, rho, v, base=U)
+
+
+def dst7_basis(n: int):
+    """(lambda, U) of the ADST graph (the path with a unit self-loop at vertex 0): the
+    DST-VII, lambda_k = 2 - 2 cos(pi (2k+1)/(2n+1)), U[j, k] = 2/sqrt(2n+1) sin(pi (2k+1)(j+1)/(2n+1))
+    (Sec. 4.3, the DTT family; closed form of the self-loop case)."""
+    k = np.arange(n)
+    lam = 2.0 - 2.0 * np.cos(np.pi * (2 * k + 1) / (2 * n + 1))
+    j = np.arange(n)[:, None]
+    U = 2.0 / np.sqrt(2 * n + 1) * np.sin(np.pi * (2 * k[None, :] + 1) * (j + 1) / (2 * n + 1))
+    return lam, U
 
 
 # --------------------------------------------------------------------------

@@ -602,3 +602,57 @@ def test_rank_k_chain_of_cauchy_factors(n):
         assert np.abs(Xc - X).max() < 1e-9, np.abs(Xc - X).max()
         _, Xw = _chain_basis(n, rhos, vs, z_from_base=True)
         assert not (np.abs(np.abs(Xw) - np.abs(X)).max() <= 1e-3)     # NaN or far off
+
+
+# --------------------------------------------------------------------------
+# a rank-one update of a general base (Thm 3.1 / 3.2) and the DTT+ case
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [8, 64])
+def test_general_base_with_the_path_is_the_path_case(n):
+    v = workloads.unit_vector(np.random.default_rng(11 + n), n)
+    mu_p, X_p = oracle.basis(n, 0.7, v)
+    mu_g, X_g = oracle.basis_general(oracle.path_eigenvalues(n), oracle.dct2_matrix(n), 0.7, v)
+    assert np.abs(mu_p - mu_g).max() < 1e-12 and np.abs(X_p - X_g).max() < 1e-10
+
+
+@pytest.mark.parametrize("n", [8, 32, 64])
+def test_dst7_basis_is_the_adst_graph(n):
+    lam, U = oracle.dst7_basis(n)
+    e0 = np.zeros(n)
+    e0[0] = 1.0
+    L = oracle.laplacian(n, 1.0, e0)
+    assert np.abs(U.T @ U - np.eye(n)).max() < 1e-12
+    assert np.abs(L @ U - U * lam[None, :]).max() < 1e-12
+    assert np.all(np.diff(lam) > 0)
+
+
+@pytest.mark.parametrize("n", [8, 32, 64])
+def test_dtt_plus_equals_the_rank_two_path_chain(n):
+    """DTT+: a rank-one update of the ADST graph (DST-VII base) is the path graph with
+    the unit self-loop at vertex 0 and then the update, whose chain signs agree with the
+    general-base convention (the DST-VII vectors have a positive first entry)."""
+    g = np.random.default_rng(21 + n)
+    e0 = np.zeros(n)
+    e0[0] = 1.0
+    for rho, v in [(0.8, workloads.unit_vector(g, n)), oracle.candidate_update(n, 1, 2, n - 5, 1.0),
+                   (-0.3, workloads.unit_vector(g, n))]:
+        lam, U = oracle.dst7_basis(n)
+        mu_g, X_g = oracle.basis_general(lam, U, rho, v)
+        mu_c, X_c = oracle.basis_rank_k(n, [1.0, rho], [e0, v])
+        assert np.abs(mu_g - mu_c).max() < 1e-12
+        assert np.abs(X_g - X_c).max() < 1e-9
+
+
+@pytest.mark.parametrize("n", [8, 32])
+def test_general_base_random(n):
+    g = np.random.default_rng(31 + n)
+    Q, _ = np.linalg.qr(g.standard_normal((n, n)))
+    lam = np.sort(g.uniform(-1.0, 3.0, n))
+    v = workloads.unit_vector(g, n)
+    mu, X = oracle.basis_general(lam, Q, 0.9, v)
+    L = (Q * lam) @ Q.T + 0.9 * np.outer(v, v)
+    assert np.abs(X @ np.diag(mu) @ X.T - L).max() < 1e-12
+    assert np.all(lam < mu) and np.all(mu[:-1] < lam[1:])          # Lemma 4.1 interlacing
+    assert np.all(0.9 * (v @ X) > 0)
+    mu0, X0 = oracle.basis_general(lam, Q, 0.0, v)                   # rho = 0: the base itself
+    assert np.abs(mu0 - lam).max() < 1e-12 and np.abs(X0 - Q).max() < 1e-10
