@@ -393,6 +393,15 @@ def main():
         plan_ms = (time.perf_counter() - t_plan) * 1e3
         tk = time_pair(torch, lambda: pk.forward(x, out=y), lambda: pk.adjoint(y, out=xr), args.steps, args.warmup)
         pk.close()
+        # DTT+ (Sec. 4.3): a rank-one update of the ADST graph, the DST-VII as the base
+        # (general-base plan: the dense product with X^T, split-BF16)
+        lam7, U7 = oracle.dst7_basis(n)
+        pd = Plan(n, W["rho"], W["v"], dtype="f32split", base=(lam7, U7))
+        td = time_pair(torch, lambda: pd.forward(x, out=y), lambda: pd.adjoint(y, out=xr), args.steps, args.warmup)
+        pd.close()
+        comp["dtt_plus_adst_n64"] = {"ms_per_step": td[0], "value": batch * n / (td[0] * 1e-3),
+                                     "median_launch_ms": 0.5 * (td[3] + td[4]),
+                                     "base": "ADST graph (DST-VII), general-base plan, dense X^T"}
         comp["rank3_edges_n64"] = {"ms_per_step": tk[0], "value": batch * n / (tk[0] * 1e-3),
                                    "median_launch_ms": 0.5 * (tk[3] + tk[4]), "plan_ms_host": plan_ms,
                                    "updates": "3 added edges, weights U[0.5, 2]; DENSE factored split-BF16"}

@@ -146,6 +146,28 @@ dctplus_status dctplus_plan(int64_t n, double rho, const double *v_host, const d
 dctplus_status dctplus_plan_rank_k(int64_t n, int32_t k, const double *rho_host, const double *V_host,
                                    const dctplus_opts *opts, void *stream, dctplus_plan_t *out);
 
+/*
+ * Build a plan for a rank-one update of a caller's base, L = U diag(lambda) U^T + rho v v^T
+ * (Thm 3.1 holds for any symmetric base: X^T = diag(a) C(mu, lambda) diag(z) U^T with
+ * z = U^T v; Thm 3.2).  A DTT+ transform, for example, takes the ADST graph's DST-VII
+ * basis and eigenvalues as the base.
+ *   lambda_host: HOST n doubles, strictly increasing (the base eigenvalues).
+ *   U_host     : HOST n x n doubles, row-major, column k = the base eigenvector of
+ *                lambda_k (orthonormal columns; not checked).
+ *   rho, v_host: the update (HOST, n doubles).
+ * Set-up in FP64 on the GPU (secular roots with the poles lambda, the Cauchy factor, and
+ * X^T = diag(a) C diag(z) U^T formed once); the transform is the dense product with X^T
+ * (route AUTO, DENSE or GFT, not factored: a general U has no fast product here; FAST
+ * and factored are EUNSUPPORTED).  n: a power of two in [4, 4096].
+ * Conventions as for dctplus_plan with U in place of the DCT-II: rho v^T x_i > 0, and a
+ * deflated row (z_k = 0) is u_k itself.
+ * Errors: EINVAL (null or non-finite input, lambda not strictly increasing),
+ * EUNSUPPORTED, ENOMEM, ENOCONV, EDEVICE.  dctplus_grad gives dl/dx only.
+ */
+dctplus_status dctplus_plan_general(int64_t n, const double *lambda_host, const double *U_host, double rho,
+                                    const double *v_host, const dctplus_opts *opts, void *stream,
+                                    dctplus_plan_t *out);
+
 /* y = X^T x for `batch` signals (Thm 3.1; Alg. 1 on the FAST route).
  * x, y: device arrays [batch, n] of the plan's element type; x and y must not alias.
  * batch == 0 is a no-op; batch < 0 is EINVAL. */

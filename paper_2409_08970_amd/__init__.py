@@ -19,14 +19,14 @@ import ctypes
 
 from . import _binding as B
 from ._binding import (DctPlusError, dctplus_adjoint, dctplus_default_opts, dctplus_forward, dctplus_grad,
-                       dctplus_grad_noalloc, dctplus_plan_rank_k,
+                       dctplus_grad_noalloc, dctplus_plan_general, dctplus_plan_rank_k,
                        dctplus_last_error, dctplus_plan, dctplus_plan_destroy, dctplus_plan_info,
                        dctplus_plan_table, dctplus_select, dctplus_select_destroy, dctplus_select_factor,
                        dctplus_select_plan, dctplus_select_size, dctplus_select_tune, dctplus_status_string)
 
 __all__ = [
     "Plan", "DctPlusFn", "dctplus", "DctPlusError", "dctplus_plan", "dctplus_forward", "dctplus_adjoint",
-    "dctplus_grad", "dctplus_grad_noalloc", "dctplus_plan_rank_k", "dctplus_plan_info", "dctplus_plan_table", "dctplus_plan_destroy", "dctplus_status_string",
+    "dctplus_grad", "dctplus_grad_noalloc", "dctplus_plan_rank_k", "dctplus_plan_general", "dctplus_plan_info", "dctplus_plan_table", "dctplus_plan_destroy", "dctplus_status_string",
     "dctplus_last_error", "dctplus_default_opts", "SelectPlan", "dctplus_select_plan", "dctplus_select",
     "dctplus_select_factor", "dctplus_select_size", "dctplus_select_destroy", "dctplus_select_tune",
 ]
@@ -51,7 +51,9 @@ class Plan:
 
     def __init__(self, n: int, rho, v, route: str = "auto", dtype: str = "f32",
                  nufft_width: int = 0, direct_kappa: float = 0.0, defl_tol: float = 0.0, device: int = -1,
-                 stream=None, factored: bool = False):
+                 stream=None, factored: bool = False, base=None):
+        """base: None (the path graph, DCT-II) or (lambda, U) of a caller's base graph
+        (dctplus_plan_general)."""
         import numpy as np
         import torch
         o = B.dctplus_default_opts()
@@ -78,7 +80,10 @@ class Plan:
         self.device = device
         self._h = None
         with torch.cuda.device(device):
-            if self.k == 1:
+            if base is not None:
+                lam, U = base
+                _, self._h = B.dctplus_plan_general(self.n, lam, U, self.rho, self.v, o, _stream(stream))
+            elif self.k == 1:
                 _, self._h = B.dctplus_plan(self.n, self.rho, self.v, o, _stream(stream))
             else:
                 _, self._h = B.dctplus_plan_rank_k(self.n, rhos, self.v, o, _stream(stream))

@@ -31,7 +31,7 @@ EXPORTED = (
     "dctplus_plan_info", "dctplus_plan_table", "dctplus_plan_destroy", "dctplus_status_string",
     "dctplus_last_error", "dctplus_select_plan", "dctplus_select", "dctplus_select_factor",
     "dctplus_select_size", "dctplus_select_destroy", "dctplus_select_tune", "dctplus_grad_noalloc",
-    "dctplus_plan_rank_k",
+    "dctplus_plan_rank_k", "dctplus_plan_general",
 )
 
 
@@ -75,6 +75,9 @@ def load(path: str = LIB_PATH):
     lib.dctplus_plan_rank_k.argtypes = [i64, ctypes.c_int32, dp, dp, ctypes.POINTER(dctplus_opts), vp,
                                         ctypes.POINTER(vp)]
     lib.dctplus_plan_rank_k.restype = ctypes.c_int
+    lib.dctplus_plan_general.argtypes = [i64, dp, dp, ctypes.c_double, dp, ctypes.POINTER(dctplus_opts), vp,
+                                         ctypes.POINTER(vp)]
+    lib.dctplus_plan_general.restype = ctypes.c_int
     lib.dctplus_forward.argtypes = [vp, vp, vp, i64, vp]
     lib.dctplus_forward.restype = ctypes.c_int
     lib.dctplus_adjoint.argtypes = [vp, vp, vp, i64, vp]
@@ -150,6 +153,23 @@ def dctplus_plan_rank_k(n: int, rhos, V, opts: dctplus_opts | None = None, strea
                                     ctypes.byref(handle))
     if check:
         _check(st, "dctplus_plan_rank_k")
+    return st, handle
+
+
+def dctplus_plan_general(n: int, lam, U, rho: float, v, opts: dctplus_opts | None = None, stream: int = 0,
+                         check: bool = True):
+    """Returns (status, handle).  lam: n base eigenvalues; U: n x n base basis (columns)."""
+    import numpy as np
+    dp = ctypes.POINTER(ctypes.c_double)
+    la = np.ascontiguousarray(np.asarray(lam, dtype=np.float64).reshape(-1))
+    Ua = np.ascontiguousarray(np.asarray(U, dtype=np.float64).reshape(-1))
+    va = np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(-1))
+    handle = ctypes.c_void_p()
+    st = load().dctplus_plan_general(int(n), la.ctypes.data_as(dp), Ua.ctypes.data_as(dp), float(rho),
+                                     va.ctypes.data_as(dp), ctypes.byref(opts) if opts is not None else None,
+                                     ctypes.c_void_p(stream), ctypes.byref(handle))
+    if check:
+        _check(st, "dctplus_plan_general")
     return st, handle
 
 

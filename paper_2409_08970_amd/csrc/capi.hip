@@ -253,6 +253,68 @@ dctplus_status dctplus_plan_rank_k(int64_t n, int32_t k, const double *rho_host,
     return plan_create(n, k, rho_host, V_host, opts, stream, out);
 }
 
+dctplus_status dctplus_plan_general(int64_t n, const double *lambda_host, const double *U_host, double rho,
+                                    const double *v_host, const dctplus_opts *opts, void *stream,
+                                    dctplus_plan_t *out) {
+    if (!out) return fail(DCTPLUS_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (n < 2) return fail(DCTPLUS_EINVAL, "n = %lld < 2", (long long)n);
+    if (n < 4 || n > 4096 || (n & (n - 1)))
+        return fail(DCTPLUS_EUNSUPPORTED, "n = %lld: general-base plans support powers of two in [4, 4096]",
+                    (long long)n);
+    if (!lambda_host || !U_host || !v_host) return fail(DCTPLUS_EINVAL, "null lambda, U or v");
+    if (!isfinite(rho)) return fail(DCTPLUS_EINVAL, "rho is not finite");
+    for (int64_t i = 0; i < n; ++i) {
+        if (!isfinite(lambda_host[i]) || !isfinite(v_host[i]))
+            return fail(DCTPLUS_EINVAL, "lambda[%lld] or v[%lld] is not finite", (long long)i, (long long)i);
+        if (i > 0 && !(lambda_host[i] > lambda_host[i - 1]))
+            return fail(DCTPLUS_EINVAL, "lambda must be strictly increasing (index %lld)", (long long)i);
+    }
+    for (int64_t i = 0; i < n * n; ++i)
+        if (!isfinite(U_host[i])) return fail(DCTPLUS_EINVAL, "U has a non-finite entry");
+    dctplus_opts o;
+    dctplus_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.dtype < DCTPLUS_F32 || o.dtype > DCTPLUS_F32_SPLIT) return fail(DCTPLUS_EINVAL, "bad dtype %d", o.dtype);
+    if (o.route < DCTPLUS_ROUTE_AUTO || o.route > DCTPLUS_ROUTE_GFT)
+        return fail(DCTPLUS_EINVAL, "bad route %d", o.route);
+    if (o.route == DCTPLUS_ROUTE_FAST || o.factored)
+        return fail(DCTPLUS_EUNSUPPORTED, "a general base has no fast transform here: its plans apply the dense "
+                                          "product with X^T (DENSE, GFT or AUTO, not factored)");
+    if ((o.dtype == DCTPLUS_BF16 || o.dtype == DCTPLUS_F32_SPLIT) && (n < 32 || n > 64))
+        return fail(DCTPLUS_EUNSUPPORTED, "BF16 operands support n in {32, 64}");
+    if (!(o.defl_tol > 0.0)) o.defl_tol = 1e-13;
+    int dev = o.device;
+    hipError_t e;
+    if (dev < 0) {
+        if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+    } else if ((e = hipSetDevice(dev)) != hipSuccess) {
+        return hip_fail(e, "hipSetDevice");
+    }
+    dctplus_plan_s *p = new (std::nothrow) dctplus_plan_s();
+    if (!p) return fail(DCTPLUS_ENOMEM, "host allocation failed");
+    p->n = n;
+    p->logn = 0;
+    while ((1LL << p->logn) < n) ++p->logn;
+    p->rho = rho;
+    p->dtype = o.dtype;
+    p->route = DCTPLUS_ROUTE_GFT;   // the dense product with X^T
+    p->device = dev;
+    p->defl_tol = o.defl_tol;
+    p->direct_kappa = 1e5;
+    p->width = 12;
+    p->factored = 0;
+    p->rank = 1;
+    p->general = 1;
+    dctplus_status st = general_build(p, lambda_host, U_host, v_host, (hipStream_t)stream);
+    if (st != DCTPLUS_OK) {
+        dctplus_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return DCTPLUS_OK;
+}
+
 dctplus_status dctplus_forward(dctplus_plan_t p, const void *x, void *y, int64_t batch, void *stream) {
     dctplus_status st = check_io(p, x, y, batch);
     if (st != DCTPLUS_OK || batch == 0) return st;
@@ -272,8 +334,8 @@ dctplus_status dctplus_adjoint(dctplus_plan_t p, const void *y, void *x, int64_t
 dctplus_status dctplus_grad(dctplus_plan_t p, const void *y, const void *gy, int64_t batch, void *gx, double *grho,
                             double *gv, void *stream) {
     if (!p) return fail(DCTPLUS_EINVAL, "null plan");
-    if (p->rank > 1 && (grho || gv))
-        return fail(DCTPLUS_EUNSUPPORTED, "d/drho and d/dv are implemented for rank-one plans");
+    if ((p->rank > 1 || p->general) && (grho || gv))
+        return fail(DCTPLUS_EUNSUPPORTED, "d/drho and d/dv are implemented for rank-one updates of the path");
     if (p->dtype != DCTPLUS_F32 && p->dtype != DCTPLUS_F32_SPLIT)
         return fail(DCTPLUS_EUNSUPPORTED, "gradients are implemented for FP32 plans");
     if (batch < 0) return fail(DCTPLUS_EINVAL, "batch = %lld < 0", (long long)batch);
@@ -293,8 +355,8 @@ dctplus_status dctplus_grad(dctplus_plan_t p, const void *y, const void *gy, int
 dctplus_status dctplus_grad_noalloc(dctplus_plan_t p, const void *y, const void *gy, int64_t batch, void *gx,
                                     double *grho, double *gv, void *stream) {
     if (!p) return fail(DCTPLUS_EINVAL, "null plan");
-    if (p->rank > 1 && (grho || gv))
-        return fail(DCTPLUS_EUNSUPPORTED, "d/drho and d/dv are implemented for rank-one plans");
+    if ((p->rank > 1 || p->general) && (grho || gv))
+        return fail(DCTPLUS_EUNSUPPORTED, "d/drho and d/dv are implemented for rank-one updates of the path");
     if (p->dtype != DCTPLUS_F32 && p->dtype != DCTPLUS_F32_SPLIT)
         return fail(DCTPLUS_EUNSUPPORTED, "gradients are implemented for FP32 plans");
     if (batch < 0) return fail(DCTPLUS_EINVAL, "batch = %lld < 0", (long long)batch);

@@ -76,6 +76,7 @@ struct dctplus_plan_s {
     int factored;             // DENSE route keeps the DCT and the Cauchy factor apart
     int defer_dense;          // plan_build leaves the dense operands to the caller (rank-k plans)
     int rank;                 // number of rank-one updates (1 for dctplus_plan)
+    int general;              // base basis given by the caller (dctplus_plan_general)
     void *dev_mem;            // one allocation holding every table
     size_t dev_bytes;
     // workspaces (FAST-route scratch for large n, the factored route's DCT output above
@@ -105,7 +106,13 @@ dctplus_status dense_apply(dctplus_plan_s *p, const void *in, void *out, int64_t
                            hipStream_t s);
 dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s);
 // dense operands from a given FP64 Cauchy factor (row-major n x n) instead of the plan's
-dctplus_status dense_build_from(dctplus_plan_s *p, const double *src, hipStream_t s);
+// (src_is_xt: src is X^T itself, applied as the folded product)
+dctplus_status dense_build_from(dctplus_plan_s *p, const double *src, hipStream_t s, bool src_is_xt = false);
+// the plan's device tables, allocated and the twiddle tables filled (no spectrum)
+dctplus_status plan_alloc_tables(dctplus_plan_s *p, hipStream_t s);
+// L = U diag(lambda) U^T + rho v v^T for a caller's base (Thm 3.1 on a general base; rankk.hip)
+dctplus_status general_build(dctplus_plan_s *p, const double *lam_host, const double *U_host, const double *v_host,
+                             hipStream_t s);
 // M = diag(a) C(mu, lambda) diag(z) of a rank-one plan, FP64 row-major n x n
 void launch_cauchy_f64(const dctplus_plan_s *p, double *M, hipStream_t s);
 // FP64 C = A B(k, j) on MFMA: B(k, j) = P[j][k] (transb) or P[k][j]; A is [batch x n]

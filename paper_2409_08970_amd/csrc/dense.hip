@@ -1152,7 +1152,7 @@ void dense_release(dctplus_plan_s *p) {
     p->simg = nullptr;
 }
 
-dctplus_status dense_build_from(dctplus_plan_s *p, const double *src, hipStream_t s) {
+dctplus_status dense_build_from(dctplus_plan_s *p, const double *src, hipStream_t s, bool src_is_xt) {
     const int n = (int)p->n;
     const size_t elems = (size_t)n * n;
     hipError_t e;
@@ -1165,11 +1165,12 @@ dctplus_status dense_build_from(dctplus_plan_s *p, const double *src, hipStream_
             return fail(DCTPLUS_ENOMEM, "hipMalloc for the %d x %d FP64 dense factor failed", n, n);
         }
         p->t.folded = 1;
-        const size_t lds = dense_rows_lds(n, true);
+        const int gft64 = src_is_xt ? 0 : 1;
+        const size_t lds = dense_rows_lds(n, gft64 != 0);
         if (lds > 65536 && (e = hipFuncSetAttribute((const void *)k_dense_rows,
                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
             return hip_fail(e, "dense factor build (LDS size)");
-        hipLaunchKernelGGL(k_dense_rows, dim3(n), dim3(256), lds, s, p->t, 1, (float *)nullptr,
+        hipLaunchKernelGGL(k_dense_rows, dim3(n), dim3(256), lds, s, p->t, gft64, (float *)nullptr,
                            (uint16_t *)nullptr, p->t.mt64, src);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "dense factor build");
@@ -1191,8 +1192,8 @@ dctplus_status dense_build_from(dctplus_plan_s *p, const double *src, hipStream_
     }
     // The DCT is folded into the factor (P = M U^T = X^T, Thm 3.1) unless the
     // factored progressive form is requested; both give the same transform.
-    p->t.folded = (p->route == DCTPLUS_ROUTE_GFT) || !p->factored;
-    const int gft = p->t.folded ? 1 : 0;
+    p->t.folded = (p->route == DCTPLUS_ROUTE_GFT) || !p->factored || src_is_xt;
+    const int gft = (p->t.folded && !src_is_xt) ? 1 : 0;
     const size_t lds = dense_rows_lds(n, gft != 0);
     if (lds > 65536 && (e = hipFuncSetAttribute((const void *)k_dense_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                 (int)lds)) != hipSuccess)
@@ -1204,7 +1205,7 @@ dctplus_status dense_build_from(dctplus_plan_s *p, const double *src, hipStream_
     return stream_images(p, s);
 }
 
-dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s) { return dense_build_from(p, nullptr, s); }
+dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s) { return dense_build_from(p, nullptr, s, false); }
 
 void launch_cauchy_f64(const dctplus_plan_s *p, double *M, hipStream_t s) {
     hipLaunchKernelGGL(k_dense_rows, dim3((unsigned)p->n), dim3(256), 0, s, p->t, 0, (float *)nullptr,

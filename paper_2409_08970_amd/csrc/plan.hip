@@ -433,7 +433,14 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
-dctplus_status plan_build(dctplus_plan_s *p, const double *v_host, hipStream_t s) {
+// Scratch of the rank-one set-up, carved from the plan's table allocation.
+struct PlanScratch {
+    double *v_dev, *misc, *r_tau, *r_a;
+    int32_t *J, *r_o;
+};
+
+// Every table of the plan in one device allocation, the twiddle and sine tables filled.
+dctplus_status plan_alloc(dctplus_plan_s *p, PlanScratch &sc, hipStream_t s) {
     const int n = (int)p->n;
     const int w = p->width;
     PlanTables &t = p->t;
@@ -478,10 +485,29 @@ dctplus_status plan_build(dctplus_plan_s *p, const double *v_host, hipStream_t s
     t.rowOfBin = rowOfBin;
     t.rowOfK = rowOfK;
     if ((e = hipMemsetAsync(t.status, 0, sizeof(int32_t) * 8, s)) != hipSuccess) return hip_fail(e, "memset");
+    hipLaunchKernelGGL(k_tables, dim3((4 * n + 255) / 256), dim3(256), 0, s, t);
+    sc = PlanScratch{v_dev, misc, r_tau, r_a, J, r_o};
+    return DCTPLUS_OK;
+}
+
+dctplus_status plan_alloc_tables(dctplus_plan_s *p, hipStream_t s) {
+    PlanScratch sc;
+    return plan_alloc(p, sc, s);
+}
+
+dctplus_status plan_build(dctplus_plan_s *p, const double *v_host, hipStream_t s) {
+    const int n = (int)p->n;
+    PlanTables &t = p->t;
+    PlanScratch sc;
+    dctplus_status ast = plan_alloc(p, sc, s);
+    if (ast != DCTPLUS_OK) return ast;
+    double *v_dev = sc.v_dev, *misc = sc.misc, *r_tau = sc.r_tau, *r_a = sc.r_a;
+    int32_t *J = sc.J, *r_o = sc.r_o, *rowOfBin = t.rowOfBin, *rowOfK = t.rowOfK;
+    const size_t nd = sizeof(double) * n;
+    hipError_t e;
     if ((e = hipMemcpyAsync(v_dev, v_host, nd, hipMemcpyHostToDevice, s)) != hipSuccess)
         return hip_fail(e, "copy v");
 
-    hipLaunchKernelGGL(k_tables, dim3((4 * n + 255) / 256), dim3(256), 0, s, t);
     const size_t lds_z = sizeof(cplx<double>) * (n / 2) > sizeof(int) * kPlanThreads
                              ? sizeof(cplx<double>) * (n / 2)
                              : sizeof(int) * kPlanThreads;

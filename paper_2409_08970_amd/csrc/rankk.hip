@@ -15,6 +15,10 @@
 //   X_k^T = C_k U^T,
 // so the transform is applied as for a rank-one plan (DCT-II, then one dense product
 // with C_k, or C_k folded with the DCT at plan time).
+//
+// The same stage kernels serve a rank-one update of a caller's base L_base = U diag(lambda)
+// U^T (Thm 3.1 holds for any symmetric base; Thm 3.2): z = U^T v, the secular roots with
+// the poles lambda, and X^T = W^T U^T formed in FP64, applied as a dense product.
 #include <vector>
 
 #include "fft.h"
@@ -42,6 +46,18 @@ __global__ void __launch_bounds__(kRkThreads) k_rk_dct(PlanTables t, const doubl
         u[k] = Xk;
         if (k > 0 && k < M) u[n - k] = XNk;
     }
+}
+
+// z = U^T v (U row-major n x n, column k = u_k), FP64; one wave per k.
+__global__ void __launch_bounds__(256) k_rk_gemv_t(const double *__restrict__ U, const double *__restrict__ v,
+                                                   double *__restrict__ z, int n) {
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (k >= n) return;
+    double s = 0.0;
+    for (int j = lane; j < n; j += 64) s += U[(size_t)j * n + k] * v[j];
+    s = wave_sum(s);
+    if (lane == 0) z[k] = s;
 }
 
 // z = C u (C row-major n x n, FP64); one wave per row.
@@ -374,6 +390,81 @@ dctplus_status rank_k_build(dctplus_plan_s *p, int k, const double *rho_host, co
     }
     ret = dense_build_from(p, C, s);
     return done(ret);
+}
+
+}  // namespace dctplus
+
+namespace dctplus {
+
+dctplus_status general_build(dctplus_plan_s *p, const double *lam_host, const double *U_host, const double *v_host,
+                             hipStream_t s) {
+    const int n = (int)p->n;
+    dctplus_status st0 = plan_alloc_tables(p, s);
+    if (st0 != DCTPLUS_OK) return st0;
+    PlanTables &t = p->t;
+    const size_t nn = (size_t)n * n, nd = sizeof(double) * n;
+    const size_t mat = sizeof(double) * nn;
+    const size_t bytes = 3 * mat + 9 * nd + 4 * sizeof(int32_t) * n + 64 * sizeof(int32_t) + 64;
+    char *buf = nullptr;
+    hipError_t e = hipMalloc(&buf, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DCTPLUS_ENOMEM, "hipMalloc(%zu) for the general-base set-up failed", bytes);
+    }
+    double *U = (double *)buf, *W = U + nn, *Xt = W + nn;
+    double *v = Xt + nn, *z = v + n, *d = z + n, *mu = d + n, *a = mu + n, *tau = a + n;
+    double *r_tau = tau + n, *r_a = r_tau + n, *misc = r_a + n;
+    int32_t *J = (int32_t *)(misc + n), *kind = J + n, *origin = kind + n, *r_o = origin + n;
+    int32_t *st = r_o + n;
+    auto done = [&](dctplus_status r) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(buf);
+        return r;
+    };
+    if ((e = hipMemsetAsync(st, 0, sizeof(int32_t) * 4, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(U, U_host, mat, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(d, lam_host, nd, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(v, v_host, nd, hipMemcpyHostToDevice, s)) != hipSuccess)
+        return done(hip_fail(e, "general-base inputs"));
+    const double rho = p->rho;
+    hipLaunchKernelGGL(k_rk_gemv_t, dim3((n + 3) / 4), dim3(256), 0, s, (const double *)U, (const double *)v, z, n);
+    if ((e = hipMemcpyAsync(t.zraw, z, nd, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+        return done(hip_fail(e, "general-base z"));
+    hipLaunchKernelGGL(k_rk_deflate, dim3(1), dim3(kRkThreads), 0, s, z, n, rho, p->defl_tol, J, st, misc);
+    hipLaunchKernelGGL(k_rk_roots, dim3((n + 3) / 4), dim3(256), 0, s, (const double *)d, (const double *)z,
+                       (const int32_t *)J, st, (const double *)misc, rho, r_o, r_tau, r_a);
+    hipLaunchKernelGGL(k_rk_rows, dim3(1), dim3(kRkThreads), sizeof(int) * (n + 1), s, (const double *)d,
+                       (const double *)z, n, rho, (const int32_t *)st, st, (const double *)misc, (const int32_t *)r_o,
+                       (const double *)r_tau, (const double *)r_a, mu, a, kind, origin, tau);
+    hipLaunchKernelGGL(k_rk_factor, dim3(n), dim3(256), 0, s, (const double *)d, (const double *)z, n,
+                       (const double *)a, (const int32_t *)kind, (const int32_t *)origin, (const double *)tau, W);
+    // X^T = W^T U^T:  X^T[i][j] = sum_k W^T[i][k] U[j][k]
+    gemm64(W, U, Xt, n, n, true, s);
+    if ((e = hipGetLastError()) != hipSuccess) return done(hip_fail(e, "general-base kernels"));
+    int32_t sth[4];
+    std::vector<int32_t> kh(n);
+    if ((e = hipMemcpyAsync(sth, st, sizeof(sth), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(kh.data(), kind, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return done(hip_fail(e, "general-base status"));
+    if (sth[1] & 1) return done(fail(DCTPLUS_ENOCONV, "secular solver did not converge"));
+    if (sth[1] & 4)
+        return done(fail(DCTPLUS_EDEGENERATE, "two base eigenvalues coincide and v touches both directions"));
+    if (sth[1] & 2) return done(fail(DCTPLUS_EDEVICE, "internal error: row order is not a permutation"));
+    t.nj = sth[0];
+    t.ntie = sth[2];
+    t.ndirect = 0;
+    int ndefl = 0;
+    for (int i = 0; i < n; ++i) ndefl += (kh[i] == ROW_DEFLATED);
+    t.ndefl = ndefl;
+    if ((e = hipMemcpyAsync(t.mu, mu, nd, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(t.a, a, nd, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(t.z, z, nd, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(t.kind, kind, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(t.origin, origin, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(t.tau, tau, nd, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+        return done(hip_fail(e, "general-base tables"));
+    return done(dense_build_from(p, Xt, s, true));
 }
 
 }  // namespace dctplus

@@ -165,3 +165,26 @@ def test_rank_k_plan_rejects_bad_arguments_on_host(lib):
     o.route = B.DCTPLUS_ROUTE_FAST
     assert B.dctplus_plan_rank_k(n, [1.0, 1.0], V, o, check=False)[0] == B.DCTPLUS_EUNSUPPORTED
     assert lib.dctplus_plan_rank_k(n, 2, None, None, None, None, None) == B.DCTPLUS_EINVAL
+
+
+def test_general_plan_rejects_bad_arguments_on_host(lib):
+    from paper_2409_08970_amd import _binding as B
+    n = 16
+    lam = np.arange(n, dtype=np.float64)
+    U = np.eye(n)
+    v = np.ones(n) / 4.0
+    lam_bad = lam.copy()
+    lam_bad[5] = lam_bad[4]
+    assert B.dctplus_plan_general(n, lam_bad, U, 1.0, v, check=False)[0] == B.DCTPLUS_EINVAL
+    U_bad = U.copy()
+    U_bad[2, 3] = np.nan
+    assert B.dctplus_plan_general(n, lam, U_bad, 1.0, v, check=False)[0] == B.DCTPLUS_EINVAL
+    assert B.dctplus_plan_general(12, np.arange(12.0), np.eye(12), 1.0, np.ones(12), check=False)[0] == \
+        B.DCTPLUS_EUNSUPPORTED
+    o = B.dctplus_default_opts()
+    o.route = B.DCTPLUS_ROUTE_FAST
+    assert B.dctplus_plan_general(n, lam, U, 1.0, v, o, check=False)[0] == B.DCTPLUS_EUNSUPPORTED
+    o = B.dctplus_default_opts()
+    o.factored = 1
+    assert B.dctplus_plan_general(n, lam, U, 1.0, v, o, check=False)[0] == B.DCTPLUS_EUNSUPPORTED
+    assert lib.dctplus_plan_general(n, None, None, ctypes.c_double(1.0), None, None, None, None) == B.DCTPLUS_EINVAL
