@@ -152,6 +152,18 @@ def bench_selection(torch, dev, steps, warmup):
         ev[k][1].record()
     torch.cuda.synchronize()
     ms = sum(a.elapsed_time(b) for a, b in ev) / reps
+
+    def pass_ms(tau):
+        ev2 = [_events(torch) for _ in range(reps)]
+        for k in range(reps):
+            ev2[k][0].record()
+            sel.select(x, prune_tau=tau, out=y)
+            ev2[k][1].record()
+        torch.cuda.synchronize()
+        return sum(a.elapsed_time(b) for a, b in ev2) / reps
+    # Thm 3.4's saving: the same pass with no signal pruned (tau = -1) and with every
+    # signal pruned (tau = 10)
+    ms_none, ms_all = pass_ms(-1.0), pass_ms(10.0)
     n64 = nb.astype(np.int64)
     samples = int(np.sum(n64 * S))
     flops = float(np.sum((K + 1) * S * 2 * n64 * n64))          # K candidate products + the winner's
@@ -164,6 +176,9 @@ def bench_selection(torch, dev, steps, warmup):
             "kernel": "k_select (persistent, FP32 MFMA)", "ms_per_pass": ms, "blocks_per_s": len(nb) / (ms * 1e-3),
             "signal_samples_per_s": samples / (ms * 1e-3), "pruned_fraction": pruned / (len(nb) * S),
             "plan_ms_host": plan_ms,
+            "pruning": {"ms_per_pass_tau_minus1_none_pruned": ms_none, "ms_per_pass_tau10_all_pruned": ms_all,
+                        "speedup_all_pruned_vs_none": ms_none / ms_all,
+                        "speedup_tau0.1_vs_none": ms_none / ms},
             "autotune": {"workgroups_per_cu": chosen, "ms_per_pass_by_candidate": tune_ms},
             "roofline": {"mfma_tflops": flops / (ms * 1e-3) / 1e12, "mfma_peak_tflops": 157.3,
                          "hbm_gbs": bytes_ / (ms * 1e-3) / 1e9, "hbm_peak_gbs": HBM_PEAK_GBS,

@@ -221,6 +221,29 @@ dctplus_status dctplus_grad_noalloc(dctplus_plan_t plan, const void *y, const vo
                                     double *grho, double *gv, void *stream);
 
 /*
+ * Launch autotuner of the transform (forward and adjoint).  For `batch` signals it times
+ * every launch configuration the plan's route offers (HIP events on `stream`, one warm-up
+ * and three calls each) and keeps the fastest in the plan for batches of the same size
+ * bucket floor(log2 batch), per direction:
+ *   streaming dense kernels (n <= 64): persistent workgroups per CU, 1..4;
+ *   the dense product above n = 64: GEMM tiles 64 x 64 or 128 x 128;
+ *   FAST: signals per workgroup, the built-in count, a half or a quarter of it.
+ * Every configuration computes the same transform (the dense kernels give the same bits;
+ * FAST may differ in rounding within its bar).
+ *   x, y       : DEVICE scratch arrays [batch, n] of the plan's type; both are overwritten.
+ *   cache_path : NULL, or a file that receives the choices as a JSON object keyed by device
+ *                architecture, n, route, dtype, form, direction and batch bucket (merged
+ *                with what the file holds).  Plans created while the environment variable
+ *                DCTPLUS_TUNE_CACHE names such a file start with its matching choices.
+ *   chosen     : HOST int32[2] (nullable): the configuration ids kept (0: nothing to tune).
+ *   ms         : HOST float[16] (nullable): mean ms per call, [direction][config id - 1].
+ * Synchronises `stream`; not for use under graph capture.  Errors: as dctplus_forward;
+ * EINVAL when the cache file cannot be written (the plan keeps its choices).
+ */
+dctplus_status dctplus_tune(dctplus_plan_t plan, void *x, void *y, int64_t batch, void *stream,
+                            const char *cache_path, int32_t *chosen, float *ms);
+
+/*
  * Copy plan tables to HOST arrays (synchronous; for tests and tools).
  * Any pointer may be NULL.  mu, a: n doubles in row order (a_i = 1 for
  * deflated rows); z: n doubles, U^T v after deflation; kind: n int32 per row
@@ -233,7 +256,9 @@ dctplus_status dctplus_plan_info(dctplus_plan_t plan, double *mu, double *a, dou
 /* Copy one named plan table to HOST memory (synchronous; for tests and tools).
  * name: "z", "zraw", "mu", "a", "tau", "hz", "deconv", "rowA", "rowB", "win", "direct",
  *       "sintab" (double); "origin", "kind", "ref", "m0", "rowOfBin", "rowOfK", "direct_row",
- *       "ntie" (one value: the number of secular roots tying a deflated lambda) (int32).  *bytes: capacity of dst on input, size of the table on output;
+ *       "ntie" (one value: the number of secular roots tying a deflated lambda) (int32);
+ *       "tune": int8 [2][64], the launch configuration dctplus_tune chose per direction
+ *       (0 forward, 1 adjoint) and batch bucket floor(log2 batch), 0 = built-in.  *bytes: capacity of dst on input, size of the table on output;
  *       dst may be NULL to query the size.  Unknown name: EINVAL. */
 dctplus_status dctplus_plan_table(dctplus_plan_t plan, const char *name, void *dst, int64_t *bytes);
 

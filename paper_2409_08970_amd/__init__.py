@@ -19,14 +19,14 @@ import ctypes
 
 from . import _binding as B
 from ._binding import (DctPlusError, dctplus_adjoint, dctplus_default_opts, dctplus_forward, dctplus_grad,
-                       dctplus_grad_noalloc, dctplus_plan_general, dctplus_plan_rank_k,
+                       dctplus_grad_noalloc, dctplus_plan_general, dctplus_plan_rank_k, dctplus_tune,
                        dctplus_last_error, dctplus_plan, dctplus_plan_destroy, dctplus_plan_info,
                        dctplus_plan_table, dctplus_select, dctplus_select_destroy, dctplus_select_factor,
                        dctplus_select_plan, dctplus_select_size, dctplus_select_tune, dctplus_status_string)
 
 __all__ = [
     "Plan", "DctPlusFn", "dctplus", "DctPlusError", "dctplus_plan", "dctplus_forward", "dctplus_adjoint",
-    "dctplus_grad", "dctplus_grad_noalloc", "dctplus_plan_rank_k", "dctplus_plan_general", "dctplus_plan_info", "dctplus_plan_table", "dctplus_plan_destroy", "dctplus_status_string",
+    "dctplus_grad", "dctplus_grad_noalloc", "dctplus_plan_rank_k", "dctplus_plan_general", "dctplus_tune", "dctplus_plan_info", "dctplus_plan_table", "dctplus_plan_destroy", "dctplus_status_string",
     "dctplus_last_error", "dctplus_default_opts", "SelectPlan", "dctplus_select_plan", "dctplus_select",
     "dctplus_select_factor", "dctplus_select_size", "dctplus_select_destroy", "dctplus_select_tune",
 ]
@@ -130,6 +130,16 @@ class Plan:
         B.dctplus_grad(self._h, y.data_ptr(), gy.data_ptr(), y.numel() // self.n,
                        gx.data_ptr() if gx is not None else 0, grho.data_ptr(), gv.data_ptr(), _stream(stream))
         return gx, grho, gv
+
+    def tune(self, x, cache_path=None, stream=None):
+        """Launch autotuner for batches the size of x ([batch, n] device tensor, left
+        unchanged): returns (chosen [forward, adjoint], ms per config)."""
+        import torch
+        x = self._check(x)
+        a, b = x.clone(), torch.empty_like(x)
+        _, chosen, ms = B.dctplus_tune(self._h, a.data_ptr(), b.data_ptr(), x.numel() // self.n, _stream(stream),
+                                       cache_path)
+        return chosen, ms
 
     def close(self):
         if self._h:

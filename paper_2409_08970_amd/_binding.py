@@ -31,7 +31,7 @@ EXPORTED = (
     "dctplus_plan_info", "dctplus_plan_table", "dctplus_plan_destroy", "dctplus_status_string",
     "dctplus_last_error", "dctplus_select_plan", "dctplus_select", "dctplus_select_factor",
     "dctplus_select_size", "dctplus_select_destroy", "dctplus_select_tune", "dctplus_grad_noalloc",
-    "dctplus_plan_rank_k", "dctplus_plan_general",
+    "dctplus_plan_rank_k", "dctplus_plan_general", "dctplus_tune",
 )
 
 
@@ -78,6 +78,9 @@ def load(path: str = LIB_PATH):
     lib.dctplus_plan_general.argtypes = [i64, dp, dp, ctypes.c_double, dp, ctypes.POINTER(dctplus_opts), vp,
                                          ctypes.POINTER(vp)]
     lib.dctplus_plan_general.restype = ctypes.c_int
+    lib.dctplus_tune.argtypes = [vp, vp, vp, i64, vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_float)]
+    lib.dctplus_tune.restype = ctypes.c_int
     lib.dctplus_forward.argtypes = [vp, vp, vp, i64, vp]
     lib.dctplus_forward.restype = ctypes.c_int
     lib.dctplus_adjoint.argtypes = [vp, vp, vp, i64, vp]
@@ -173,6 +176,18 @@ def dctplus_plan_general(n: int, lam, U, rho: float, v, opts: dctplus_opts | Non
     return st, handle
 
 
+def dctplus_tune(plan, x_ptr: int, y_ptr: int, batch: int, stream: int = 0, cache_path: str | None = None,
+                 check: bool = True):
+    """Returns (status, chosen [2] ints, ms [16] floats)."""
+    chosen = (ctypes.c_int32 * 2)()
+    ms = (ctypes.c_float * 16)()
+    st = load().dctplus_tune(plan, ctypes.c_void_p(x_ptr), ctypes.c_void_p(y_ptr), int(batch),
+                             ctypes.c_void_p(stream), cache_path.encode() if cache_path else None, chosen, ms)
+    if check:
+        _check(st, "dctplus_tune")
+    return st, list(chosen), list(ms)
+
+
 def dctplus_forward(plan, x_ptr: int, y_ptr: int, batch: int, stream: int = 0, check: bool = True) -> int:
     st = load().dctplus_forward(plan, ctypes.c_void_p(x_ptr), ctypes.c_void_p(y_ptr), int(batch),
                                 ctypes.c_void_p(stream))
@@ -234,7 +249,7 @@ def dctplus_plan_table(plan, name: str):
     lib = load()
     size = ctypes.c_int64(0)
     _check(lib.dctplus_plan_table(plan, name.encode(), None, ctypes.byref(size)), "dctplus_plan_table")
-    dt = np.int32 if name in _INT_TABLES else np.float64
+    dt = np.int8 if name == "tune" else (np.int32 if name in _INT_TABLES else np.float64)
     out = np.zeros(size.value // np.dtype(dt).itemsize, dtype=dt)
     if size.value:
         _check(lib.dctplus_plan_table(plan, name.encode(), ctypes.c_void_p(out.ctypes.data), ctypes.byref(size)),

@@ -5,8 +5,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
 #include <mutex>
 #include <new>
+#include <string>
 
 #include "common.h"
 
@@ -130,6 +132,68 @@ static dctplus_status set_device(const dctplus_plan_s *p) {
     return DCTPLUS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Tuning cache: a flat JSON object {"<key>": <config id>, ...}, one entry per line, keyed
+// by device architecture, n, route, dtype, form, direction and batch bucket.
+// ---------------------------------------------------------------------------
+static std::string tune_prefix(const dctplus_plan_s *p) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch = arch.substr(0, colon);
+    }
+    char buf[160];
+    snprintf(buf, sizeof(buf), "%s|n=%lld|route=%d|dtype=%d|factored=%d|folded=%d|", arch.c_str(), (long long)p->n,
+             p->route, p->dtype, p->factored, p->t.folded);
+    return buf;
+}
+
+static std::map<std::string, int> cache_read(const char *path) {
+    std::map<std::string, int> m;
+    FILE *f = fopen(path, "r");
+    if (!f) return m;
+    char line[512];
+    while (fgets(line, sizeof(line), f)) {
+        const char *a = strchr(line, '"');
+        if (!a) continue;
+        const char *b = strchr(a + 1, '"');
+        if (!b) continue;
+        const char *c = strchr(b, ':');
+        if (!c) continue;
+        m[std::string(a + 1, b)] = atoi(c + 1);
+    }
+    fclose(f);
+    return m;
+}
+
+static bool cache_write(const char *path, const std::map<std::string, int> &m) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    fprintf(f, "{\n");
+    size_t i = 0;
+    for (const auto &kv : m) fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < m.size() ? "," : "");
+    fprintf(f, "}\n");
+    const bool ok = fclose(f) == 0;
+    return ok && rename(tmp.c_str(), path) == 0;
+}
+
+// Entries of the cache named by DCTPLUS_TUNE_CACHE that match this plan.
+static void cache_apply(dctplus_plan_s *p) {
+    const char *path = getenv("DCTPLUS_TUNE_CACHE");
+    if (!path || !*path) return;
+    const std::string pre = tune_prefix(p);
+    for (const auto &kv : cache_read(path)) {
+        if (kv.first.compare(0, pre.size(), pre) != 0) continue;
+        int dir = -1, bucket = -1;
+        if (sscanf(kv.first.c_str() + pre.size(), "dir=%d|bucket=%d", &dir, &bucket) != 2) continue;
+        if (dir < 0 || dir > 1 || bucket < 0 || bucket > 63 || kv.second < 0 || kv.second > 8) continue;
+        p->tune_cfg[dir][bucket] = (int8_t)kv.second;
+    }
+}
+
 }  // namespace dctplus
 
 using namespace dctplus;
@@ -239,6 +303,7 @@ static dctplus_status plan_create(int64_t n, int32_t k, const double *rhos, cons
         dctplus_plan_destroy(p);
         return st;
     }
+    cache_apply(p);
     *out = p;
     return DCTPLUS_OK;
 }
@@ -311,6 +376,7 @@ dctplus_status dctplus_plan_general(int64_t n, const double *lambda_host, const 
         dctplus_plan_destroy(p);
         return st;
     }
+    cache_apply(p);
     *out = p;
     return DCTPLUS_OK;
 }
@@ -376,6 +442,75 @@ dctplus_status dctplus_grad_noalloc(dctplus_plan_t p, const void *y, const void 
                              kStaticScratchBytes, (hipStream_t)stream);
 }
 
+dctplus_status dctplus_tune(dctplus_plan_t p, void *x, void *y, int64_t batch, void *stream, const char *cache_path,
+                            int32_t *chosen, float *ms) {
+    dctplus_status st = check_io(p, x, y, batch);
+    if (st != DCTPLUS_OK) return st;
+    if (batch == 0) return fail(DCTPLUS_EINVAL, "batch = 0: nothing to time");
+    if ((st = set_device(p)) != DCTPLUS_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int count = (p->route == DCTPLUS_ROUTE_FAST) ? fast_tune_count(p) : dense_tune_count(p, batch);
+    const int b = batch_bucket(batch);
+    if (ms)
+        for (int i = 0; i < 16; ++i) ms[i] = 0.0f;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail(e, "tuner events");
+    }
+    int best[2] = {0, 0};
+    for (int dir = 0; dir < 2 && st == DCTPLUS_OK; ++dir) {
+        const bool adj = dir == 1;
+        float best_ms = 0.0f;
+        for (int c = 1; c <= count && count > 1 && st == DCTPLUS_OK; ++c) {
+            p->tune_cfg[dir][b] = (int8_t)c;
+            auto call = [&]() {
+                return adj ? dctplus_adjoint(p, y, x, batch, stream) : dctplus_forward(p, x, y, batch, stream);
+            };
+            if ((st = call()) != DCTPLUS_OK) break;                      // warm-up
+            if ((e = hipEventRecord(e0, s)) != hipSuccess) { st = hip_fail(e, "tuner event"); break; }
+            for (int r = 0; r < 3 && st == DCTPLUS_OK; ++r) st = call();
+            if (st != DCTPLUS_OK) break;
+            float t = 0.0f;
+            if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+                (e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) {
+                st = hip_fail(e, "tuner timing");
+                break;
+            }
+            t /= 3.0f;
+            if (ms && c <= 8) ms[8 * dir + c - 1] = t;
+            if (best[dir] == 0 || t < best_ms) {
+                best[dir] = c;
+                best_ms = t;
+            }
+        }
+        p->tune_cfg[dir][b] = (int8_t)best[dir];
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != DCTPLUS_OK) {
+        p->tune_cfg[0][b] = p->tune_cfg[1][b] = 0;
+        return st;
+    }
+    if (chosen) {
+        chosen[0] = best[0];
+        chosen[1] = best[1];
+    }
+    if (cache_path && *cache_path && count > 1) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);   // serialises writers in this process
+        auto m = cache_read(cache_path);
+        const std::string pre = tune_prefix(p);
+        for (int dir = 0; dir < 2; ++dir) {
+            char k[64];
+            snprintf(k, sizeof(k), "dir=%d|bucket=%d", dir, b);
+            m[pre + k] = best[dir];
+        }
+        if (!cache_write(cache_path, m)) return fail(DCTPLUS_EINVAL, "cannot write the tuning cache %s", cache_path);
+    }
+    return DCTPLUS_OK;
+}
+
 dctplus_status dctplus_plan_info(dctplus_plan_t p, double *mu, double *a, double *z, int32_t *kind,
                                  int32_t *counts) {
     if (!p) return fail(DCTPLUS_EINVAL, "null plan");
@@ -412,6 +547,16 @@ dctplus_status dctplus_plan_table(dctplus_plan_t p, const char *name, void *dst,
         {"direct_row", p->t.direct_row, 4 * (nd < kMaxDirect ? nd : kMaxDirect)},
         {"ntie", p->t.status + 4, 4},
     };
+    if (strcmp(name, "tune") == 0) {
+        // host table: int8 [2 directions][64 batch buckets], the tuner's choices (0 = built-in)
+        const int64_t cap = *bytes;
+        *bytes = (int64_t)sizeof(p->tune_cfg);
+        if (!dst) return DCTPLUS_OK;
+        if (cap < *bytes) return fail(DCTPLUS_EINVAL, "buffer of %lld bytes is smaller than %lld", (long long)cap,
+                                      (long long)*bytes);
+        memcpy(dst, p->tune_cfg, sizeof(p->tune_cfg));
+        return DCTPLUS_OK;
+    }
     for (const Entry &e : tab) {
         if (strcmp(e.name, name) != 0) continue;
         const int64_t cap = *bytes;

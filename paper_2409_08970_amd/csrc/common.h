@@ -76,6 +76,9 @@ struct dctplus_plan_s {
     int factored;             // DENSE route keeps the DCT and the Cauchy factor apart
     int defer_dense;          // plan_build leaves the dense operands to the caller (rank-k plans)
     int rank;                 // number of rank-one updates (1 for dctplus_plan)
+    // launch configuration chosen by dctplus_tune, per direction (0 forward, 1 adjoint)
+    // and batch bucket floor(log2 batch); 0 = the built-in choice
+    int8_t tune_cfg[2][64];
     int general;              // base basis given by the caller (dctplus_plan_general)
     void *dev_mem;            // one allocation holding every table
     size_t dev_bytes;
@@ -129,6 +132,18 @@ dctplus_status grad_apply_static(dctplus_plan_s *p, const float *y, const float 
 // true when the plan's forward and adjoint need neither the plan workspace nor a library call
 bool route_alloc_free(const dctplus_plan_s *p);
 bool fast_in_lds(const dctplus_plan_s *p);
+// launch configurations the tuner may choose from for this plan and batch (ids 1..count;
+// 1 when there is nothing to choose)
+int dense_tune_count(const dctplus_plan_s *p, int64_t batch);
+int fast_tune_count(const dctplus_plan_s *p);
+inline int batch_bucket(int64_t batch) {
+    int b = 0;
+    while (b < 63 && (int64_t(2) << b) <= batch) ++b;
+    return b;
+}
+inline int tuned(const dctplus_plan_s *p, bool adjoint, int64_t batch) {
+    return p->tune_cfg[adjoint ? 1 : 0][batch_bucket(batch)];
+}
 dctplus_status plan_build(dctplus_plan_s *p, const double *v_host, hipStream_t s);
 // the workspace of stream s, at least `bytes` long (grows it: waits for s, frees, allocates)
 dctplus_status stream_work(dctplus_plan_s *p, hipStream_t s, size_t bytes, void **out);

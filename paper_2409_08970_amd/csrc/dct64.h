@@ -19,6 +19,10 @@
 // adjoint is exactly the transposed forward.
 #pragma once
 
+#ifdef __HIPCC__
+#include <hip/hip_runtime.h>
+#endif
+
 namespace dctplus {
 namespace d64 {
 
@@ -232,6 +236,32 @@ __host__ __device__ inline void special_adj(const float in[8], float T[16]) {
     T[11] = -mi;
     T[15] = -kH * (mr + pi);
 }
+
+#ifdef __HIPCC__
+// Stage 2: the 4 x 4 block transposition across the lane groups of a wave.
+__device__ __forceinline__ void xpose_lane_groups(float R[16]) {
+    // block b (R[4b .. 4b+3]) of lane group g goes to lane group b, where it lands in
+    // block g: two rounds of lane-half swaps (lanes 0-31 <-> 32-63, then rows of 16)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(R[4 * b + e]),
+                                                            __float_as_uint(R[4 * (b + 2) + e]), false, false);
+            R[4 * b + e] = __uint_as_float(r[0]);
+            R[4 * (b + 2) + e] = __uint_as_float(r[1]);
+        }
+#pragma unroll
+    for (int b = 0; b < 4; b += 2)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(R[4 * b + e]),
+                                                            __float_as_uint(R[4 * (b + 1) + e]), false, false);
+            R[4 * b + e] = __uint_as_float(r[0]);
+            R[4 * (b + 1) + e] = __uint_as_float(r[1]);
+        }
+}
+#endif
 
 }  // namespace d64
 }  // namespace dctplus

@@ -518,28 +518,6 @@ __global__ void __launch_bounds__(256, 4) k_dense_stream(const float *__restrict
 // adjoint product's output rows are the inverse DCT's input slots, so the
 // factors meet without a further exchange.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void xpose_lane_groups(float R[16]) {
-    // R[4 b + e] of lane group g -> R[4 g' + e] of lane group b (block b of g' ...)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(R[4 * b + e]),
-                                                            __float_as_uint(R[4 * (b + 2) + e]), false, false);
-            R[4 * b + e] = __uint_as_float(r[0]);
-            R[4 * (b + 2) + e] = __uint_as_float(r[1]);
-        }
-#pragma unroll
-    for (int b = 0; b < 4; b += 2)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(R[4 * b + e]),
-                                                            __float_as_uint(R[4 * (b + 1) + e]), false, false);
-            R[4 * b + e] = __uint_as_float(r[0]);
-            R[4 * (b + 1) + e] = __uint_as_float(r[1]);
-        }
-}
-
 // Operand image of the factored kernel, laid out as k_stream_image's.
 //   forward: A = M; contraction slot q of lane group g is DCT coefficient d64::out_index(g, q).
 //   adjoint: A = M^T; output row 4 g + v of tile c is coefficient d64::out_index(g, 4 c + v),
@@ -661,7 +639,7 @@ __global__ void __launch_bounds__(256, 4) k_factored_stream(const float *__restr
             }
             __builtin_amdgcn_wave_barrier();
             d64::rdft16(a, R);
-            xpose_lane_groups(R);
+            d64::xpose_lane_groups(R);
             float X[16];
             d64::group_fwd(R, 0, kA, X);
             if (g < 3) d64::group_fwd(R, 2, kB, X + 8);
@@ -685,7 +663,7 @@ __global__ void __launch_bounds__(256, 4) k_factored_stream(const float *__restr
             d64::group_adj(X, kA, R, 0);
             if (g < 3) d64::group_adj(X + 8, kB, R, 2);
             else d64::special_adj(X + 8, R);
-            xpose_lane_groups(R);
+            d64::xpose_lane_groups(R);
             float a[16];
             d64::rdft16_t(R, a);
             float *lo = stf + RS * l16 + 2 * g, *hi = stf + RS * l16 + 63 - 2 * g;
@@ -1028,45 +1006,42 @@ int persistent_blocks(int64_t nchunks) {
     return (int)(nchunks < cap ? nchunks : cap);
 }
 
-// Grid of the streaming kernel: every workgroup resident at once (the kernel
-// strides over tiles), never more workgroups than groups of four tiles.
-template <int N, int MODE>
-int stream_blocks(int64_t ntiles) {
-    static int cap = 0;
-    if (cap == 0) {
+// Grid of the streaming kernels: persistent workgroups, at most the resident capacity (or
+// `wpc` per CU when the tuner chose it), never more than one per four tiles.
+template <typename K>
+int persistent_grid(K kernel, int &cap_cache, int &per_cache, int64_t ntiles, int wpc) {
+    if (cap_cache == 0) {
         int per = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_dense_stream<N, MODE>, 256, 0) != hipSuccess ||
-            per <= 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess || per <= 0) {
             (void)hipGetLastError();
             per = 2;
         }
-        cap = per * num_cus();
+        per_cache = per;
+        cap_cache = per * num_cus();
     }
+    const int64_t cap = (wpc > 0 && wpc < per_cache) ? (int64_t)wpc * num_cus() : cap_cache;
     const int64_t want = (ntiles + 3) / 4;
     return (int)(want < cap ? want : cap);
+}
+
+template <int N, int MODE>
+int stream_blocks(int64_t ntiles, int wpc) {
+    static int cap = 0, per = 0;
+    return persistent_grid(k_dense_stream<N, MODE>, cap, per, ntiles, wpc);
 }
 
 template <int MODE, bool ADJ>
-int factored_blocks(int64_t ntiles) {
-    static int cap = 0;
-    if (cap == 0) {
-        int per = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_factored_stream<MODE, ADJ>, 256, 0) != hipSuccess ||
-            per <= 0) {
-            (void)hipGetLastError();
-            per = 2;
-        }
-        cap = per * num_cus();
-    }
-    const int64_t want = (ntiles + 3) / 4;
-    return (int)(want < cap ? want : cap);
+int factored_blocks(int64_t ntiles, int wpc) {
+    static int cap = 0, per = 0;
+    return persistent_grid(k_factored_stream<MODE, ADJ>, cap, per, ntiles, wpc);
 }
 
 // The FP32 dense product for n > 64: 128 x 128 tiles when they give at least two
-// workgroups per CU, 64 x 64 otherwise (small batches).
-void launch_gemm32(const float *A, const float *P, float *C, int64_t M, int n, bool transb, hipStream_t s) {
+// workgroups per CU, 64 x 64 otherwise (small batches); cfg 1 / 2 force 64 / 128.
+void launch_gemm32(const float *A, const float *P, float *C, int64_t M, int n, bool transb, int cfg, hipStream_t s) {
     const int64_t big = ((M + 127) / 128) * (n / 128);
-    if (n % 128 == 0 && big >= 2 * num_cus()) {
+    const bool t128 = n % 128 == 0 && (cfg == 2 || (cfg == 0 && big >= 2 * num_cus()));
+    if (t128) {
         const dim3 grid((unsigned)(n / 128), (unsigned)((M + 127) / 128));
         if (transb) hipLaunchKernelGGL((k_gemm32<128, 128, true>), grid, dim3(256), 0, s, A, P, C, M, n);
         else hipLaunchKernelGGL((k_gemm32<128, 128, false>), grid, dim3(256), 0, s, A, P, C, M, n);
@@ -1207,6 +1182,14 @@ dctplus_status dense_build_from(dctplus_plan_s *p, const double *src, hipStream_
 
 dctplus_status dense_build(dctplus_plan_s *p, hipStream_t s) { return dense_build_from(p, nullptr, s, false); }
 
+int dense_tune_count(const dctplus_plan_s *p, int64_t batch) {
+    const int n = (int)p->n;
+    if (p->dtype == DCTPLUS_F64 || n <= 8) return 1;
+    if (n <= 64) return (p->simg != nullptr) ? 4 : 1;   // streaming kernels: 1..4 workgroups per CU
+    (void)batch;
+    return (n % 128 == 0) ? 2 : 1;                       // GEMM tiles 64 x 64 or 128 x 128
+}
+
 void launch_cauchy_f64(const dctplus_plan_s *p, double *M, hipStream_t s) {
     hipLaunchKernelGGL(k_dense_rows, dim3((unsigned)p->n), dim3(256), 0, s, p->t, 0, (float *)nullptr,
                        (uint16_t *)nullptr, M, (const double *)nullptr);
@@ -1226,6 +1209,7 @@ dctplus_status dense_apply(dctplus_plan_s *p, const void *inv, void *outv, int64
     const int adj = adjoint ? 1 : 0;
     const bool bf = (p->dtype == DCTPLUS_BF16);
     const bool split = (p->dtype == DCTPLUS_F32_SPLIT);
+    const int cfg = tuned(p, adjoint, batch);   // 0: built-in launch choice
     if (p->dtype == DCTPLUS_F64) {
         // y = X^T x (or x = X y) as one FP64 product with the folded factor
         if (batch > (int64_t)65535 * TBM) return fail(DCTPLUS_EINVAL, "batch too large for the FP64 dense route");
@@ -1259,7 +1243,7 @@ dctplus_status dense_apply(dctplus_plan_s *p, const void *inv, void *outv, int64
             const unsigned char *img = (const unsigned char *)p->simg + (adj ? p->simg_bytes : 0);
             const d64::GroupConst *kc = (const d64::GroupConst *)((const unsigned char *)p->simg + 2 * p->simg_bytes);
 #define DCTPLUS_FACTORED(MM, AA)                                                                        \
-    hipLaunchKernelGGL((k_factored_stream<MM, AA>), dim3(factored_blocks<MM, AA>(ntiles)), dim3(256), 0, s, in, \
+    hipLaunchKernelGGL((k_factored_stream<MM, AA>), dim3(factored_blocks<MM, AA>(ntiles, cfg)), dim3(256), 0, s, in, \
                        out, batch, img, kc)
             if (split) {
                 if (adj) DCTPLUS_FACTORED(2, true);
@@ -1283,7 +1267,7 @@ dctplus_status dense_apply(dctplus_plan_s *p, const void *inv, void *outv, int64
             if (!p->simg) return fail(DCTPLUS_EDEVICE, "no streaming operand image on this plan");
             const unsigned char *img = (const unsigned char *)p->simg + (adj ? p->simg_bytes : 0);
 #define DCTPLUS_STREAM(NN, MM)                                                                             \
-    hipLaunchKernelGGL((k_dense_stream<NN, MM>), dim3(stream_blocks<NN, MM>(ntiles)), dim3(256), 0, s, in, out, \
+    hipLaunchKernelGGL((k_dense_stream<NN, MM>), dim3(stream_blocks<NN, MM>(ntiles, cfg)), dim3(256), 0, s, in, out, \
                        batch, img)
             if (split) {
                 if (n == 32) DCTPLUS_STREAM(32, 2);
@@ -1315,10 +1299,10 @@ dctplus_status dense_apply(dctplus_plan_s *p, const void *inv, void *outv, int64
                 hipLaunchKernelGGL(k_dct_rows, dgrid, dim3(256), lds, s, p->t, in, tmp, batch, 0, nsig);
                 A = tmp;
             }
-            launch_gemm32(A, p->t.mt32, out, batch, n, true, s);      // y_b = P x_b
+            launch_gemm32(A, p->t.mt32, out, batch, n, true, cfg, s);      // y_b = P x_b
         } else {
             float *C = pre ? tmp : out;
-            launch_gemm32(in, p->t.mt32, C, batch, n, false, s);      // x_b = P^T y_b
+            launch_gemm32(in, p->t.mt32, C, batch, n, false, cfg, s);      // x_b = P^T y_b
             if (pre) hipLaunchKernelGGL(k_dct_rows, dgrid, dim3(256), lds, s, p->t, tmp, out, batch, 1, nsig);
         }
     }

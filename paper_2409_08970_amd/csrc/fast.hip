@@ -429,7 +429,8 @@ __global__ void __launch_bounds__(1024) k_fast_adj(PlanTables t, const TIO *__re
     }
 }
 
-FastCfg fast_config(const dctplus_plan_s *p) {
+// cfg (the tuner's choice): 0 or 1 = the built-in signals per workgroup, 2 = half, 3 = a quarter
+FastCfg fast_config(const dctplus_plan_s *p, int cfg = 0) {
     const int n = (int)p->n;
     const int nd = p->t.ndirect;
     const size_t tdsz = (p->dtype == DCTPLUS_F64) ? 8 : 4;
@@ -449,6 +450,7 @@ FastCfg fast_config(const dctplus_plan_s *p) {
     // keep the register staging of the grid post-processing bounded
     while (ns > 1 && (size_t)ns * n > (size_t)kMaxPair * c.threads) ns >>= 1;
     while (ns > 1 && (size_t)ns * ((c.big_in_lds ? per_big : 0) + per_small) > budget) ns >>= 1;
+    if (cfg >= 2) ns = ns >> (cfg - 1) > 0 ? ns >> (cfg - 1) : 1;
     c.nsig = ns;
     c.lds = (size_t)ns * ((c.big_in_lds ? per_big : 0) + per_small) + 64 + 8 * 16;   // + exact-row partials
     return c;
@@ -469,9 +471,14 @@ void launch_fast(dctplus_plan_s *p, const FastCfg &c, dim3 grid, dim3 block, con
 
 bool fast_in_lds(const dctplus_plan_s *p) { return fast_config(p).big_in_lds; }
 
+int fast_tune_count(const dctplus_plan_s *p) {
+    const int ns = fast_config(p, 0).nsig;
+    return ns >= 4 ? 3 : (ns >= 2 ? 2 : 1);
+}
+
 dctplus_status fast_apply(dctplus_plan_s *p, const void *in, void *out, int64_t batch, bool adjoint,
                           hipStream_t s) {
-    const FastCfg c = fast_config(p);
+    const FastCfg c = fast_config(p, tuned(p, adjoint, batch));
     const int n = (int)p->n;
     if ((size_t)c.nsig * n > (size_t)kMaxPair * c.threads)
         return fail(DCTPLUS_EUNSUPPORTED, "n = %d too large for the FAST route", n);

@@ -31,6 +31,7 @@
 #include <numeric>
 #include <vector>
 
+#include "dct64.h"
 #include "fft.h"
 
 struct dctplus_select_s {
@@ -47,6 +48,7 @@ struct dctplus_select_s {
     int32_t *status_dev = nullptr;
     float *M = nullptr;               // all factors
     float *dctm = nullptr;            // orthonormal DCT-II matrices of the five sizes (factor layout)
+    dctplus::d64::GroupConst *kc = nullptr;   // lane constants of the register DCT-II (n = 64)
     int32_t wgs_per_cu = 4;           // persistent workgroups per CU (set by dctplus_select_tune)
 };
 
@@ -252,6 +254,7 @@ struct SelArgs {
     int32_t *counter;
     const float *M;
     const float *dctm;
+    const d64::GroupConst *kc;
     int64_t nblocks;
     int K, S, cp;
     double tau;
@@ -261,9 +264,13 @@ struct SelArgs {
 };
 
 struct SelShared {
-    float xs[kSelMaxS * (kSelMaxN + 1)];     // signals, then their DCT-II (row stride n + 1)
+    float xs[kSelMaxS * (kSelMaxN + 1)];     // signals, then their DCT-II in slot order (row stride n + 1)
     float cost[kSelMaxK];
-    int pruned[kSelMaxS];
+    int pruned[kSelMaxS];                    // per signal
+    int slot_of[kSelMaxS];                   // slot of each signal: pruned signals first
+    int sig_of[kSelMaxS];                    // signal of each slot
+    int spr[kSelMaxS];                       // pruned flag per slot
+    int npr;                                 // number of pruned signals (slots 0 .. npr - 1)
     int next;
     int best;
 };
@@ -273,9 +280,29 @@ struct SelShared {
 // MFMA (each lane reads its samples before any lane of the wave writes, and the
 // wave touches only its own rows).  n < 16: thread s < 64 transforms signal s.
 template <int N>
-__device__ __forceinline__ void sel_dct(SelShared &sh, const float *__restrict__ D) {
+__device__ __forceinline__ void sel_dct(SelShared &sh, const float *__restrict__ D, const d64::GroupConst *kc) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if constexpr (N >= 16) {
+    if constexpr (N == 64) {
+        // radix DCT-II in registers (dct64.h): lane (l16, g) of wave w holds sixteen samples of
+        // signal 16 w + l16 and ends with sixteen of its coefficients
+        const int l16 = lane & 15, g = lane >> 4;
+        const int sig = 16 * wave + l16;
+        const float *row = sh.xs + sig * (N + 1);
+        float a[16], R[16], X[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) a[m] = row[d64::in_index(g, m)];
+        __syncthreads();                         // every signal is read before slots are written
+        d64::rdft16(a, R);
+        d64::xpose_lane_groups(R);
+        const d64::GroupConst kA = kc[2 * g], kB = kc[2 * g + 1];
+        d64::group_fwd(R, 0, kA, X);
+        if (g < 3) d64::group_fwd(R, 2, kB, X + 8);
+        else d64::special_fwd(R, X + 8);
+        float *out = sh.xs + sh.slot_of[sig] * (N + 1);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) out[d64::out_index(g, q)] = X[q];
+        (void)D;
+    } else if constexpr (N >= 16) {
         constexpr int CT = N / 16, KS = N / 4;
         const int l16 = lane & 15, g = lane >> 4;
         const float4 *D4 = reinterpret_cast<const float4 *>(D);
@@ -298,15 +325,18 @@ __device__ __forceinline__ void sel_dct(SelShared &sh, const float *__restrict__
                 }
             }
         }
-        // lane holds coefficients i = 16 c + 4 g + v of its signal
+        // lane holds coefficients i = 16 c + 4 g + v of its signal; written to its slot
+        __syncthreads();                         // every signal is read before slots are written
+        float *out = sh.xs + sh.slot_of[16 * wave + l16] * (N + 1);
 #pragma unroll
         for (int c = 0; c < CT; ++c)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) row[16 * c + 4 * g + v] = acc[c][v];
+            for (int v = 0; v < 4; ++v) out[16 * c + 4 * g + v] = acc[c][v];
     } else {
+        float sd[N];
         if (threadIdx.x < 64) {
-            float *row = sh.xs + threadIdx.x * (N + 1);
-            float xv[N], sd[N];
+            const float *row = sh.xs + threadIdx.x * (N + 1);
+            float xv[N];
 #pragma unroll
             for (int j = 0; j < N; ++j) xv[j] = row[j];
 #pragma unroll
@@ -316,8 +346,12 @@ __device__ __forceinline__ void sel_dct(SelShared &sh, const float *__restrict__
                 for (int j = 0; j < N; ++j) acc += D[i * N + j] * xv[j];
                 sd[i] = acc;
             }
+        }
+        __syncthreads();                         // every signal is read before slots are written
+        if (threadIdx.x < 64) {
+            float *out = sh.xs + sh.slot_of[threadIdx.x] * (N + 1);
 #pragma unroll
-            for (int i = 0; i < N; ++i) row[i] = sd[i];
+            for (int i = 0; i < N; ++i) out[i] = sd[i];
         }
     }
 }
@@ -344,20 +378,35 @@ __device__ __forceinline__ float sel_cost_mfma(const SelShared &sh, const float 
             a[c][4 * s4 + 3] = q.w;
         }
     float l1 = 0.f;
+    const int npr = sh.npr;
 #pragma unroll 1
     for (int tile = 0; tile < kSelMaxS / 16; ++tile) {
-        const int sig = 16 * tile + l16;
-        const bool pr = sh.pruned[sig] != 0;
+        const int slot = 16 * tile + l16;           // slots hold the pruned signals first
+        const bool pr = sh.spr[slot] != 0;
         f4 acc[CT];
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[c] = f4{0.f, 0.f, 0.f, 0.f};
+        if (16 * (tile + 1) <= npr && cp == N / 2) {
+            // sixteen pruned signals: only the c_p x c_p block (Thm 3.4), output tiles
+            // c < c_p / 16 and contraction k < c_p, a quarter of the MFMAs
+            constexpr int CTP = CT / 2 > 0 ? CT / 2 : 1;
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            const int k = 4 * s + g;
-            float bv = sh.xs[sig * (N + 1) + k];
-            if (pr && k >= cp) bv = 0.f;
+            for (int s = 0; s < KS / 2; ++s) {
+                const float bv = sh.xs[slot * (N + 1) + 4 * s + g];
 #pragma unroll
-            for (int c = 0; c < CT; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c][s], bv, acc[c], 0, 0, 0);
+                for (int c = 0; c < CTP; ++c)
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c][s], bv, acc[c], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const int k = 4 * s + g;
+                float bv = sh.xs[slot * (N + 1) + k];
+                if (pr && k >= cp) bv = 0.f;
+#pragma unroll
+                for (int c = 0; c < CT; ++c)
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c][s], bv, acc[c], 0, 0, 0);
+            }
         }
         // this lane holds outputs i = 16 c + 4 g + v of signal sig
 #pragma unroll
@@ -387,7 +436,7 @@ __device__ __forceinline__ float sel_tiles(const SelShared &sh, const float *__r
     f4 acc[CT];
 #pragma unroll
     for (int j = 0; j < CT; ++j) {
-        pr[j] = sh.pruned[16 * (grp + j * G) + l16] != 0;
+        pr[j] = sh.spr[16 * (grp + j * G) + l16] != 0;
         acc[j] = f4{0.f, 0.f, 0.f, 0.f};
     }
 #pragma unroll
@@ -411,8 +460,7 @@ __device__ __forceinline__ float sel_tiles(const SelShared &sh, const float *__r
 #pragma unroll
     for (int j = 0; j < CT; ++j) {
         const int t = grp + j * G;
-        if (t >= ntile) continue;
-        const int sig = 16 * t + l16;
+        const int sig = sh.sig_of[16 * t + l16];    // the slot's signal (rows past S are zero)
         float v4[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -431,11 +479,11 @@ __device__ __forceinline__ float sel_tiles(const SelShared &sh, const float *__r
 template <int N>
 __device__ __forceinline__ float sel_product_valu(const SelShared &sh, const float *__restrict__ Mr, int cp, int S,
                                                   float *__restrict__ yout) {
-    const int sig = threadIdx.x & 63;
-    const bool pr = sh.pruned[sig] != 0;
+    const int slot = threadIdx.x & 63, sig = sh.sig_of[slot];
+    const bool pr = sh.spr[slot] != 0;
     float sd[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) sd[k] = (pr && k >= cp) ? 0.f : sh.xs[sig * (N + 1) + k];
+    for (int k = 0; k < N; ++k) sd[k] = (pr && k >= cp) ? 0.f : sh.xs[slot * (N + 1) + k];
     float l1 = 0.f;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -470,10 +518,20 @@ __device__ __forceinline__ void sel_block(SelShared &sh, const SelArgs &A, int64
             q += d * d;
             e2 += (double)row[j] * row[j];
         }
-        sh.pruned[tid] = (q <= A.tau * e2) ? 1 : 0;
+        const int pr = (q <= A.tau * e2) ? 1 : 0;
+        sh.pruned[tid] = pr;
+        // slots: pruned signals first, each group in signal order (wave 0 holds the 64 signals)
+        const uint64_t mask = __ballot(pr);
+        const int np = __popcll(mask);
+        const int before = __popcll(mask & ((uint64_t(1) << tid) - 1));
+        const int slot = pr ? before : np + (tid - before);
+        sh.slot_of[tid] = slot;
+        sh.sig_of[slot] = tid;
+        sh.spr[slot] = pr;
+        if (tid == 0) sh.npr = np;
     }
     __syncthreads();                            // the pruning test has read the raw rows
-    sel_dct<N>(sh, A.dctm + sel_dct_offset(N));
+    sel_dct<N>(sh, A.dctm + sel_dct_offset(N), A.kc);
     __syncthreads();
     const int cp = (A.cp <= 0) ? (N / 2 > 2 ? N / 2 : 2) : (A.cp < N ? A.cp : N);
     const int ntile = (S + 15) / 16;
@@ -604,6 +662,7 @@ dctplus_status dctplus_select_plan(int64_t nblocks, int32_t K, int32_t S, const 
         hipMalloc(&p->order_dev, sizeof(int32_t) * nblocks) != hipSuccess ||
         hipMalloc(&p->counter_dev, 256) != hipSuccess || hipMalloc(&p->status_dev, 256) != hipSuccess ||
         hipMalloc(&p->dctm, sizeof(float) * sel_dct_offset(2 * kSelMaxN)) != hipSuccess ||
+        hipMalloc(&p->kc, sizeof(d64::GroupConst) * 8) != hipSuccess ||
         hipMalloc(&p->M, sizeof(float) * (size_t)ma) != hipSuccess ||
         hipMalloc(&cand_dev, sizeof(double) * 4 * (size_t)nblocks * K) != hipSuccess) {
         (void)hipGetLastError();
@@ -611,6 +670,11 @@ dctplus_status dctplus_select_plan(int64_t nblocks, int32_t K, int32_t S, const 
                          (long long)ma));
     }
     int32_t st = 0;
+    // lane constants of the register DCT-II (lane group g: frequency groups 2g + 1, 2g + 2)
+    d64::GroupConst kch[8];
+    for (int t = 0; t < 8; ++t) kch[t] = d64::group_const((t >> 1) * 2 + 1 + (t & 1));
+    if ((e = hipMemcpyAsync(p->kc, kch, sizeof(kch), hipMemcpyHostToDevice, s)) != hipSuccess)
+        return bail(hip_fail(e, "selection plan upload"));
     if ((e = hipMemcpyAsync(p->n_dev, n_host, sizeof(int32_t) * nblocks, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(p->xoff_dev, p->xoff_host.data(), sizeof(int64_t) * nblocks, hipMemcpyHostToDevice,
                             s)) != hipSuccess ||
@@ -665,6 +729,7 @@ dctplus_status dctplus_select(dctplus_select_t p, const float *x, int32_t c_p, d
     A.counter = p->counter_dev;
     A.M = p->M;
     A.dctm = p->dctm;
+    A.kc = p->kc;
     A.nblocks = p->nblocks;
     A.K = p->K;
     A.S = p->S;
@@ -757,6 +822,7 @@ void dctplus_select_destroy(dctplus_select_t p) {
     if (p->counter_dev) (void)hipFree(p->counter_dev);
     if (p->status_dev) (void)hipFree(p->status_dev);
     if (p->dctm) (void)hipFree(p->dctm);
+    if (p->kc) (void)hipFree(p->kc);
     if (p->M) (void)hipFree(p->M);
     delete p;
 }
