@@ -22,16 +22,30 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into one shared library (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc", *FLAGS, "-o", tmp, *sources(), *LIBS]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError("hipcc failed building libdctplus.so")
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP source (one hipcc per source, in parallel) and link them
+    into one shared library.  Always recompiles."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    jobs = max(1, min(len(sources()), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with tempfile.TemporaryDirectory(prefix="dctplus_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.basename(src) + ".o") for src in sources()]
+        with ThreadPoolExecutor(max_workers=jobs) as ex:
+            for f in [ex.submit(_run, ["hipcc", *compile_flags, "-c", src, "-o", obj], verbose)
+                      for src, obj in zip(sources(), objs)]:
+                f.result()
+        tmp = LIB + ".tmp"
+        _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, *LIBS], verbose)
     os.replace(tmp, LIB)
     return LIB
 

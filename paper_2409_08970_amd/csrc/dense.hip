@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(256) k_dense_rows(PlanTables t, int gft, float
         // row i of X^T = (U m_i)^T: inverse orthonormal DCT of the row of M
         cplx<double> *Z = reinterpret_cast<cplx<double> *>(smem);
         const int logT = logn + 2;
-        for (int k = tid; k < n / 2; k += nthr) Z[k] = dct3_pack<double>(entry, k, logn, t.tw64, logT);
+        for (int k = tid; k < n / 2; k += nthr) Z[fft_slot<double>(k)] = dct3_pack<double>(entry, k, logn, t.tw64, logT);
         __syncthreads();
         const RadixPlan rp = radix_plan(logn - 1, 1, nthr);
         fft_dif(Z, 1, n / 2, logn - 1, t.tw64, logT, rp);
@@ -108,7 +108,7 @@ __device__ __forceinline__ void tile_dct(float *xs, cplx<float> *Z, const cplx<f
     if (dir == 0) {
         for (int g = tid; g < kChunk * M; g += nthr) {
             const int s = g / M, m = g % M;
-            Z[s * M + m] = dct2_pack<float>(xs + s * SmallLds<N>::kPad, m, N);
+            Z[s * M + fft_slot<float>(m)] = dct2_pack<float>(xs + s * SmallLds<N>::kPad, m, N);
         }
         __syncthreads();
         fft_dif(Z, kChunk, M, logN - 1, tw, logT, rp);
@@ -124,7 +124,7 @@ __device__ __forceinline__ void tile_dct(float *xs, cplx<float> *Z, const cplx<f
             const int s = g / M, k = g % M;
             const float *row = xs + s * SmallLds<N>::kPad;
             auto get = [&](int kk) -> float { return row[kk]; };
-            Z[s * M + k] = dct3_pack<float>(get, k, logN, tw, logT);
+            Z[s * M + fft_slot<float>(k)] = dct3_pack<float>(get, k, logN, tw, logT);
         }
         __syncthreads();
         fft_dif(Z, kChunk, M, logN - 1, tw, logT, rp);
@@ -793,7 +793,7 @@ __global__ void __launch_bounds__(256) k_dct_rows(PlanTables t, const float *__r
     if (dir == 0) {
         for (int g = tid; g < ns * M; g += nthr) {
             const int s = g / M, m = g % M;
-            Z[(size_t)s * M + m] = dct2_pack<float>(in + (s0 + s) * n, m, n);
+            Z[(size_t)s * M + fft_slot<float>(m)] = dct2_pack<float>(in + (s0 + s) * n, m, n);
         }
         __syncthreads();
         fft_dif(Z, ns, M, logn - 1, t.tw32, logT, rp);
@@ -809,7 +809,7 @@ __global__ void __launch_bounds__(256) k_dct_rows(PlanTables t, const float *__r
             const int s = g / M, k = g % M;
             const float *row = in + (s0 + s) * n;
             auto get = [&](int kk) -> float { return row[kk]; };
-            Z[(size_t)s * M + k] = dct3_pack<float>(get, k, logn, t.tw32, logT);
+            Z[(size_t)s * M + fft_slot<float>(k)] = dct3_pack<float>(get, k, logn, t.tw32, logT);
         }
         __syncthreads();
         fft_dif(Z, ns, M, logn - 1, t.tw32, logT, rp);

@@ -38,7 +38,7 @@ namespace {
 constexpr int kExt = 16;      // grid extension on each side (>= max window half-width)
 constexpr int kMaxPair = 16;  // register staging per thread in the grid post-processing
 
-__host__ __device__ inline int big_doubles(int n) {
+__host__ __device__ constexpr int big_doubles(int n) {
     // per-signal FP64 buffer: 2n complex doubles, and room for the extended grid
     int d = 4 * n;
     const int need = 2 * n + 2 * kExt + 2;
@@ -46,11 +46,30 @@ __host__ __device__ inline int big_doubles(int n) {
     return (d + 1) & ~1;
 }
 
+// threads per workgroup and the most signals one workgroup transforms, per n = 2^logn
+// (both compile-time constants of the kernels; the host may pick fewer signals)
+__host__ __device__ constexpr int fast_threads(int logn) { return logn <= 8 ? 256 : 1024; }
+__host__ __device__ constexpr int fast_nsig_max(int logn) {
+    const int n = 1 << logn, thr = fast_threads(logn);
+    int ns = n <= 256 ? 1024 / n : 4096 / n;
+    if (ns < 1) ns = 1;
+    // keep the register staging of the grid post-processing bounded
+    while (ns > 1 && ns * n > kMaxPair * thr) ns >>= 1;
+    return ns;
+}
+// buffer placements the kernels are built for: in LDS up to n = 4096, in global
+// scratch from n = 2048 on
+constexpr int kMaxLogLds = 12, kMinLogGlobal = 11;
+
 struct FastCfg {
     int nsig, threads;
     bool big_in_lds;
     size_t lds;
 };
+
+// double d of a signal's complex FP64 FFT buffer, the place where the real
+// transforms write their odd extensions, under the bank swizzle of the FFT
+__device__ __forceinline__ int dslot(int d) { return 2 * fft_slot<double>(d >> 1) + (d & 1); }
 
 // grid value at any integer position from the base values G_0..G_2n (odd, period 4n)
 __device__ __forceinline__ double grid_fold(const double *Gb, int p, int n) {
@@ -60,16 +79,20 @@ __device__ __forceinline__ double grid_fold(const double *Gb, int p, int n) {
     return r <= 2 * n ? Gb[r] : -Gb[P - r];
 }
 
-template <typename TIO, typename TD, bool kLds>
-__global__ void __launch_bounds__(1024) k_fast_fwd(PlanTables t, const TIO *__restrict__ x, TIO *__restrict__ y,
+template <int LOGN, typename TIO, typename TD, bool kLds>
+__global__ void __launch_bounds__(fast_threads(LOGN)) k_fast_fwd(PlanTables t, const TIO *__restrict__ x, TIO *__restrict__ y,
                                                    int64_t batch, int nsig, double *__restrict__ gscratch) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int n = t.n, logn = t.logn, w = t.width, tid = threadIdx.x, nthr = blockDim.x;
+    constexpr int n = 1 << LOGN, logn = LOGN, nthr = fast_threads(LOGN), BD = big_doubles(n);
+    // signals the radix plans are made for, and the register staging rounds
+    constexpr int kPlanSig = fast_nsig_max(LOGN);
+    constexpr int kRounds = (kPlanSig * n + nthr - 1) / nthr;
+    static_assert(kRounds <= kMaxPair, "staging rounds");
+    const int w = t.width, tid = threadIdx.x;
     const int nd = t.ndirect;
     const int64_t s0 = (int64_t)blockIdx.x * nsig;
     const int ns = (int)((batch - s0) < nsig ? (batch - s0) : nsig);
-    const int BD = big_doubles(n);
-    const int logT = logn + 2;
+    constexpr int logT = logn + 2;
     double *big;
     if constexpr (kLds)
         big = reinterpret_cast<double *>(smem);
@@ -88,10 +111,10 @@ __global__ void __launch_bounds__(1024) k_fast_fwd(PlanTables t, const TIO *__re
     cplx<TD> *Zf = reinterpret_cast<cplx<TD> *>(big);
     for (int g = tid; g < ns * (n / 2); g += nthr) {
         const int s = g / (n / 2), m = g % (n / 2);
-        Zf[(size_t)s * strideZ + m] = dct2_pack<TD>(x + (s0 + s) * n, m, n);
+        Zf[(size_t)s * strideZ + fft_slot<TD>(m)] = dct2_pack<TD>(x + (s0 + s) * n, m, n);
     }
     __syncthreads();
-    const RadixPlan rpA = radix_plan(logn - 1, ns, nthr);
+    constexpr RadixPlan rpA = radix_plan(logn - 1, kPlanSig, nthr);
     fft_dif(Zf, ns, strideZ, logn - 1, twd, logT, rpA);
     for (int g = tid; g < ns * (n / 2 + 1); g += nthr) {
         const int s = g / (n / 2 + 1), k = g % (n / 2 + 1);
@@ -113,10 +136,10 @@ __global__ void __launch_bounds__(1024) k_fast_fwd(PlanTables t, const TIO *__re
             if (q < n) return t.hz[q] * (double)sds[q];
             return -t.hz[2 * n - q] * (double)sds[2 * n - q];
         };
-        Bc[(size_t)s * strideB + n / 2 + m] = {u(2 * m), u(2 * m + 1)};
+        Bc[(size_t)s * strideB + n / 2 + fft_slot<double>(m)] = {u(2 * m), u(2 * m + 1)};
     }
     __syncthreads();
-    const RadixPlan rpB = radix_plan(logn, ns, nthr);
+    constexpr RadixPlan rpB = radix_plan(logn, kPlanSig, nthr);
     fft_dif(Bc + n / 2, ns, strideB, logn, t.tw64, logT, rpB);
 
     // 3. c = DST-I(h), times the window deconvolution; written as the odd
@@ -129,23 +152,23 @@ __global__ void __launch_bounds__(1024) k_fast_fwd(PlanTables t, const TIO *__re
             continue;
         }
         const double c = dst1_post(Bc + (size_t)s * strideB + n / 2, l, logn, rpB, t.tw64, logT) * t.deconv[l];
-        q[l] = c;
-        q[4 * n - l] = -c;
+        q[dslot(l)] = c;
+        q[dslot(4 * n - l)] = -c;
     }
     __syncthreads();
     for (int g = tid; g < ns * (2 * n + 1); g += nthr) {
         const int s = g / (2 * n + 1), p = g % (2 * n + 1);
-        big[(size_t)s * BD + n + p] = 0.0;
+        big[(size_t)s * BD + dslot(n + p)] = 0.0;
     }
     __syncthreads();
 
     // 4. grid G_m = sum_l chat_l sin(pi l m / 2n), m = 0..2n (DST-I of length 2n)
-    const RadixPlan rpC = radix_plan(logn + 1, ns, nthr);
+    constexpr RadixPlan rpC = radix_plan(logn + 1, kPlanSig, nthr);
     fft_dif(Bc, ns, strideB, logn + 1, t.tw64, logT, rpC);
     // pairs (m, 2n - m), m = 1..n, staged in registers (the output overwrites the FFT data)
-    double gv[2 * kMaxPair];
+    double gv[2 * kRounds];
 #pragma unroll
-    for (int it = 0; it < kMaxPair; ++it) {
+    for (int it = 0; it < kRounds; ++it) {
         const int g = tid + it * nthr;
         if (g < ns * n) {
             const int s = g / n, m = g % n + 1;
@@ -156,7 +179,7 @@ __global__ void __launch_bounds__(1024) k_fast_fwd(PlanTables t, const TIO *__re
     }
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < kMaxPair; ++it) {
+    for (int it = 0; it < kRounds; ++it) {
         const int g = tid + it * nthr;
         if (g < ns * n) {
             const int s = g / n, m = g % n + 1;
@@ -242,16 +265,20 @@ __global__ void __launch_bounds__(1024) k_fast_fwd(PlanTables t, const TIO *__re
     }
 }
 
-template <typename TIO, typename TD, bool kLds>
-__global__ void __launch_bounds__(1024) k_fast_adj(PlanTables t, const TIO *__restrict__ y, TIO *__restrict__ x,
+template <int LOGN, typename TIO, typename TD, bool kLds>
+__global__ void __launch_bounds__(fast_threads(LOGN)) k_fast_adj(PlanTables t, const TIO *__restrict__ y, TIO *__restrict__ x,
                                                    int64_t batch, int nsig, double *__restrict__ gscratch) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int n = t.n, logn = t.logn, w = t.width, tid = threadIdx.x, nthr = blockDim.x;
+    constexpr int n = 1 << LOGN, logn = LOGN, nthr = fast_threads(LOGN), BD = big_doubles(n);
+    // signals the radix plans are made for, and the register staging rounds
+    constexpr int kPlanSig = fast_nsig_max(LOGN);
+    constexpr int kRounds = (kPlanSig * n + nthr - 1) / nthr;
+    static_assert(kRounds <= kMaxPair, "staging rounds");
+    const int w = t.width, tid = threadIdx.x;
     const int nd = t.ndirect;
     const int64_t s0 = (int64_t)blockIdx.x * nsig;
     const int ns = (int)((batch - s0) < nsig ? (batch - s0) : nsig);
-    const int BD = big_doubles(n);
-    const int logT = logn + 2;
+    constexpr int logT = logn + 2;
     double *big;
     if constexpr (kLds)
         big = reinterpret_cast<double *>(smem);
@@ -342,14 +369,14 @@ __global__ void __launch_bounds__(1024) k_fast_adj(PlanTables t, const TIO *__re
             double *q = big + (size_t)s * BD;
             if (p == 0) {
                 q[0] = 0.0;
-                q[2 * n] = 0.0;
+                q[dslot(2 * n)] = 0.0;
                 continue;
             }
             double G = Gv[h];
             if (p <= hw) G -= gather(s, -p);
             if (p >= 2 * n - hw) G -= gather(s, 4 * n - p);
-            q[p] = G;
-            q[4 * n - p] = -G;
+            q[dslot(p)] = G;
+            q[dslot(4 * n - p)] = -G;
         }
     }
     if (wps > 1) {
@@ -363,14 +390,14 @@ __global__ void __launch_bounds__(1024) k_fast_adj(PlanTables t, const TIO *__re
     __syncthreads();
     cplx<double> *Bc = reinterpret_cast<cplx<double> *>(big);
     const int strideB = BD / 2;
-    const RadixPlan rpC = radix_plan(logn + 1, ns, nthr);
+    constexpr RadixPlan rpC = radix_plan(logn + 1, kPlanSig, nthr);
     fft_dif(Bc, ns, strideB, logn + 1, t.tw64, logT, rpC);
 
     // r_l = sum_m G'_m sin(pi l m / 2n) for l < n, times the deconvolution;
     // staged in registers, then written as the odd extension (length 2n) for DST-I
-    double cv[kMaxPair];
+    double cv[kRounds];
 #pragma unroll
-    for (int it = 0; it < kMaxPair; ++it) {
+    for (int it = 0; it < kRounds; ++it) {
         const int g = tid + it * nthr;
         if (g < ns * n) {
             const int s = g / n, l = g % n;
@@ -381,22 +408,22 @@ __global__ void __launch_bounds__(1024) k_fast_adj(PlanTables t, const TIO *__re
     }
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < kMaxPair; ++it) {
+    for (int it = 0; it < kRounds; ++it) {
         const int g = tid + it * nthr;
         if (g < ns * n) {
             const int s = g / n, l = g % n;
             double *q = big + (size_t)s * BD;
             if (l == 0) {
                 q[0] = 0.0;
-                q[n] = 0.0;
+                q[dslot(n)] = 0.0;
             } else {
-                q[l] = cv[it];
-                q[2 * n - l] = -cv[it];
+                q[dslot(l)] = cv[it];
+                q[dslot(2 * n - l)] = -cv[it];
             }
         }
     }
     __syncthreads();
-    const RadixPlan rpB = radix_plan(logn, ns, nthr);
+    constexpr RadixPlan rpB = radix_plan(logn, kPlanSig, nthr);
     fft_dif(Bc, ns, strideB, logn, t.tw64, logT, rpB);
 
     // s_d' = hz * DST-I(c') + deflated rows + exact rows + the compensation, in doubles [2n, 3n)
@@ -418,10 +445,10 @@ __global__ void __launch_bounds__(1024) k_fast_adj(PlanTables t, const TIO *__re
         const int s = g / (n / 2), k = g % (n / 2);
         const double *sds = big + (size_t)s * BD + 2 * n;
         auto get = [&](int kk) -> TD { return (TD)sds[kk]; };
-        Zf[(size_t)s * strideZ + k] = dct3_pack<TD>(get, k, logn, twd, logT);
+        Zf[(size_t)s * strideZ + fft_slot<TD>(k)] = dct3_pack<TD>(get, k, logn, twd, logT);
     }
     __syncthreads();
-    const RadixPlan rpA = radix_plan(logn - 1, ns, nthr);
+    constexpr RadixPlan rpA = radix_plan(logn - 1, kPlanSig, nthr);
     fft_dif(Zf, ns, strideZ, logn - 1, twd, logT, rpA);
     for (int g = tid; g < ns * n; g += nthr) {
         const int s = g / n, j = g % n;
@@ -435,7 +462,7 @@ FastCfg fast_config(const dctplus_plan_s *p, int cfg = 0) {
     const int nd = p->t.ndirect;
     const size_t tdsz = (p->dtype == DCTPLUS_F64) ? 8 : 4;
     FastCfg c;
-    c.threads = n <= 256 ? 256 : 1024;
+    c.threads = fast_threads(p->logn);
     const size_t per_big = sizeof(double) * big_doubles(n);
     const size_t per_small = tdsz * n + sizeof(double) * (nd + 1);
     int lds_max = 0;   // per device (a host-side query)
@@ -445,10 +472,7 @@ FastCfg fast_config(const dctplus_plan_s *p, int cfg = 0) {
     size_t budget = (size_t)lds_max - 4096;
     if (budget > 150 * 1024) budget = 150 * 1024;
     c.big_in_lds = (per_big + per_small) <= budget;
-    int ns = n <= 256 ? (1024 / n) : (4096 / n);
-    if (ns < 1) ns = 1;
-    // keep the register staging of the grid post-processing bounded
-    while (ns > 1 && (size_t)ns * n > (size_t)kMaxPair * c.threads) ns >>= 1;
+    int ns = fast_nsig_max(p->logn);
     while (ns > 1 && (size_t)ns * ((c.big_in_lds ? per_big : 0) + per_small) > budget) ns >>= 1;
     if (cfg >= 2) ns = ns >> (cfg - 1) > 0 ? ns >> (cfg - 1) : 1;
     c.nsig = ns;
@@ -456,15 +480,32 @@ FastCfg fast_config(const dctplus_plan_s *p, int cfg = 0) {
     return c;
 }
 
-template <typename TIO, typename TD, bool kLds>
-void launch_fast(dctplus_plan_s *p, const FastCfg &c, dim3 grid, dim3 block, const void *in, void *out,
-                 int64_t batch, bool adjoint, double *scratch, hipStream_t s) {
-    if (!adjoint)
-        hipLaunchKernelGGL((k_fast_fwd<TIO, TD, kLds>), grid, block, c.lds, s, p->t, (const TIO *)in, (TIO *)out,
-                           batch, c.nsig, scratch);
-    else
-        hipLaunchKernelGGL((k_fast_adj<TIO, TD, kLds>), grid, block, c.lds, s, p->t, (const TIO *)in, (TIO *)out,
-                           batch, c.nsig, scratch);
+// the kernel built for the plan's n (one instantiation per n and buffer placement)
+template <typename TIO, typename TD, bool kLds, int LOGN = 1>
+dctplus_status launch_fast(dctplus_plan_s *p, const FastCfg &c, dim3 grid, const void *in, void *out,
+                           int64_t batch, bool adjoint, double *scratch, hipStream_t s) {
+    if constexpr (LOGN > kMaxLogN) {
+        return fail(DCTPLUS_EUNSUPPORTED, "no FAST kernel for n = %lld", (long long)p->n);
+    } else {
+        if (p->logn != LOGN)
+            return launch_fast<TIO, TD, kLds, LOGN + 1>(p, c, grid, in, out, batch, adjoint, scratch, s);
+        constexpr bool built = kLds ? LOGN <= kMaxLogLds : LOGN >= kMinLogGlobal;
+        if constexpr (!built) {
+            return fail(DCTPLUS_EUNSUPPORTED, "no FAST kernel for n = %lld with the buffer %s", (long long)p->n,
+                        kLds ? "in LDS" : "in global memory");
+        } else {
+            if (c.threads != fast_threads(LOGN) || c.nsig > fast_nsig_max(LOGN))
+                return fail(DCTPLUS_EINVAL, "FAST launch shape does not match the kernel");
+            const dim3 block(fast_threads(LOGN));
+            if (!adjoint)
+                hipLaunchKernelGGL((k_fast_fwd<LOGN, TIO, TD, kLds>), grid, block, c.lds, s, p->t, (const TIO *)in,
+                                   (TIO *)out, batch, c.nsig, scratch);
+            else
+                hipLaunchKernelGGL((k_fast_adj<LOGN, TIO, TD, kLds>), grid, block, c.lds, s, p->t, (const TIO *)in,
+                                   (TIO *)out, batch, c.nsig, scratch);
+            return DCTPLUS_OK;
+        }
+    }
 }
 
 }  // namespace
@@ -490,18 +531,15 @@ dctplus_status fast_apply(dctplus_plan_s *p, const void *in, void *out, int64_t 
         if (st != DCTPLUS_OK) return st;
     }
     if (blocks > 0x7fffffff) return fail(DCTPLUS_EINVAL, "batch too large");
-    const dim3 grid((unsigned)blocks), block(c.threads);
-    if (p->dtype == DCTPLUS_F64) {
-        if (c.big_in_lds)
-            launch_fast<double, double, true>(p, c, grid, block, in, out, batch, adjoint, scratch, s);
-        else
-            launch_fast<double, double, false>(p, c, grid, block, in, out, batch, adjoint, scratch, s);
-    } else {
-        if (c.big_in_lds)
-            launch_fast<float, float, true>(p, c, grid, block, in, out, batch, adjoint, scratch, s);
-        else
-            launch_fast<float, float, false>(p, c, grid, block, in, out, batch, adjoint, scratch, s);
-    }
+    const dim3 grid((unsigned)blocks);
+    dctplus_status st;
+    if (p->dtype == DCTPLUS_F64)
+        st = c.big_in_lds ? launch_fast<double, double, true>(p, c, grid, in, out, batch, adjoint, scratch, s)
+                          : launch_fast<double, double, false>(p, c, grid, in, out, batch, adjoint, scratch, s);
+    else
+        st = c.big_in_lds ? launch_fast<float, float, true>(p, c, grid, in, out, batch, adjoint, scratch, s)
+                          : launch_fast<float, float, false>(p, c, grid, in, out, batch, adjoint, scratch, s);
+    if (st != DCTPLUS_OK) return st;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "fast route launch");
     return DCTPLUS_OK;

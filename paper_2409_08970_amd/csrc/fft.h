@@ -5,8 +5,9 @@
 // passes (r <= 4).  Each pass gives every thread whole R-point butterflies
 // held in registers; passes are separated by workgroup barriers.  The output
 // is left in digit-reversed order; dif_pos() maps a frequency index to its
-// slot, and the consumers of an FFT read through it instead of paying for a
-// reordering pass.  Several independent signals (nsig, `stride` complex
+// position, and the consumers of an FFT read through it instead of paying for
+// a reordering pass.  Positions are stored bank-swizzled (fft_slot): the
+// input is written, and the output read, through fft_slot.  Several independent signals (nsig, `stride` complex
 // elements apart) are transformed by one call.  The buffer may live in LDS or
 // in global scratch; callers pass pointers whose address space the compiler
 // can see through the inlining (LDS or global), never a generic one.
@@ -84,16 +85,18 @@ __device__ __forceinline__ void dft_reg(cplx<T> *x) {
 // remain (a pass costs a barrier and a round of memory latency, so fewer,
 // wider passes win once the transform is small), smaller radices otherwise.
 // Must be computed identically by the FFT and by whoever reads its output.
+// Any plan computes the same transform; nsig and nthreads only steer the
+// choice of radices, so a plan made for more signals than a call transforms
+// is still correct.  Evaluated at compile time where its arguments are
+// constants, which turns every digit-reversal and pass loop into fixed shifts.
 struct RadixPlan {
     int np;          // number of passes
     uint32_t code;   // 2 bits per pass: log2(radix) - 1
-    __device__ __forceinline__ int lr(int i) const { return (int)((code >> (2 * i)) & 3u) + 1; }
+    __host__ __device__ constexpr int lr(int i) const { return (int)((code >> (2 * i)) & 3u) + 1; }
 };
 
-__device__ __forceinline__ RadixPlan radix_plan(int logN, int nsig, int nthreads) {
-    RadixPlan rp;
-    rp.np = 0;
-    rp.code = 0;
+__host__ __device__ constexpr RadixPlan radix_plan(int logN, int nsig, int nthreads) {
+    RadixPlan rp{0, 0u};
     int rem = logN;
     while (rem > 0) {
         int lr = rem < 4 ? rem : 4;
@@ -105,7 +108,8 @@ __device__ __forceinline__ RadixPlan radix_plan(int logN, int nsig, int nthreads
     return rp;
 }
 
-// Slot of frequency k in the digit-reversed output.
+// Position of frequency k in the digit-reversed output (kept in slot
+// fft_slot of that position).
 __device__ __forceinline__ int dif_pos(int k, const RadixPlan &rp, int logN) {
     int p = 0, logL = logN;
     uint32_t code = rp.code;
@@ -120,6 +124,25 @@ __device__ __forceinline__ int dif_pos(int k, const RadixPlan &rp, int logN) {
     return p;
 }
 
+// Bank swizzle of the FFT buffers.  Element e of a signal's buffer is kept in
+// slot fft_slot(e) = e ^ fold(e >> B), where 2^B elements fill one 256-byte row
+// of LDS banks and fold XORs all B-bit groups of its argument together.  A pass
+// with a small butterfly span, and a consumer reading in digit-reversed order,
+// step through the buffer in power-of-two strides; unswizzled, the lanes of a
+// wave would then pile onto a few banks.  fold sends each index bit above B to
+// bit (b mod B), so lanes whose indices differ in any B consecutive bits land in
+// distinct bank slots.  The map is linear over XOR and permutes every aligned
+// block of 2^B elements, so a buffer whose length is a power of two keeps its
+// extent.  Whatever fills an FFT's input or reads its output goes through it.
+template <typename T>
+__device__ __forceinline__ int fft_slot(int e) {
+    constexpr int B = sizeof(cplx<T>) >= 16 ? 4 : 5;
+    int h = e >> B;
+    h ^= h >> B;
+    h ^= h >> (2 * B);
+    return e ^ (h & ((1 << B) - 1));
+}
+
 template <int LR, typename T>
 __device__ __forceinline__ void fft_pass(cplx<T> *buf, int nsig, int stride, int logN, int logL,
                                          const cplx<T> *__restrict__ tw, int logNtw, int tid, int nthr) {
@@ -128,15 +151,21 @@ __device__ __forceinline__ void fft_pass(cplx<T> *buf, int nsig, int stride, int
     const int m = 1 << logm;
     const int lg = logN - LR;                 // log2(groups per signal)
     const int total = nsig << lg;
+    // slot offsets of the R inputs (fft_slot is linear and the butterfly's first
+    // index has no bits in common with r << logm)
+    int roff[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) roff[r] = fft_slot<T>(r << logm);
     for (int g = tid; g < total; g += nthr) {
         const int s = g >> lg;
         const int rem = g & ((1 << lg) - 1);
         const int sub = rem >> logm;
         const int j = rem & (m - 1);
-        cplx<T> *base = buf + (size_t)s * stride + (sub << logL) + j;
+        cplx<T> *sig = buf + (size_t)s * stride;
+        const int a = fft_slot<T>((sub << logL) + j);
         cplx<T> x[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) x[r] = base[r << logm];
+        for (int r = 0; r < R; ++r) x[r] = sig[a ^ roff[r]];
         dft_reg<LR>(x);
         if (logm > 0) {
             // twiddles w^r, w = exp(-2 pi i j / L): w, w^4 and w^8 come from the table and
@@ -171,7 +200,7 @@ __device__ __forceinline__ void fft_pass(cplx<T> *buf, int nsig, int stride, int
             }
         }
 #pragma unroll
-        for (int r = 0; r < R; ++r) base[r << logm] = x[r];
+        for (int r = 0; r < R; ++r) sig[a ^ roff[r]] = x[r];
     }
 }
 
@@ -201,7 +230,8 @@ __device__ __forceinline__ void fft_dif(cplx<T> *buf, int nsig, int stride, int 
 // ---------------------------------------------------------------------------
 
 // Makhoul reordering for the DCT-II: v_q = x_{2q} (q < N/2), v_{N-1-q} = x_{2q+1};
-// packed complex input Z_m = v_{2m} + i v_{2m+1}, m < N/2.  Returns Z_m.
+// packed complex input Z_m = v_{2m} + i v_{2m+1}, m < N/2.  Returns Z_m, to be
+// stored in slot fft_slot(m).
 template <typename T, typename Src>
 __device__ __forceinline__ cplx<T> dct2_pack(const Src *x, int m, int N) {
     auto vq = [&](int q) -> T { return q < N / 2 ? T(x[2 * q]) : T(x[2 * (N - 1 - q) + 1]); };
@@ -215,8 +245,8 @@ template <typename T>
 __device__ __forceinline__ void dct2_post(const cplx<T> *Zh, int k, int logN, const RadixPlan &rp,
                                           const cplx<T> *__restrict__ tw, int logNtw, T &Xk, T &XNk) {
     const int N = 1 << logN, M = N >> 1, logM = logN - 1;
-    const cplx<T> a = Zh[dif_pos(k & (M - 1), rp, logM)];
-    const cplx<T> b = cconj(Zh[dif_pos((M - k) & (M - 1), rp, logM)]);
+    const cplx<T> a = Zh[fft_slot<T>(dif_pos(k & (M - 1), rp, logM))];
+    const cplx<T> b = cconj(Zh[fft_slot<T>(dif_pos((M - k) & (M - 1), rp, logM))]);
     const cplx<T> E = cscale(cadd(a, b), T(0.5));
     const cplx<T> O = cdiv2i(csub(a, b));
     const cplx<T> wN = tw[(k << (logNtw - logN)) & ((1 << logNtw) - 1)];
@@ -228,7 +258,7 @@ __device__ __forceinline__ void dct2_post(const cplx<T> *Zh, int k, int logN, co
     XNk = -P.im * c1;
 }
 
-// Inverse of the above: for 0 <= k < M = N/2, the FFT input Zh_k (natural order,
+// Inverse of the above: for 0 <= k < M = N/2, the FFT input Zh_k (slot fft_slot(k),
 // conjugated so that a forward FFT performs the inverse) built from the
 // orthonormal coefficients X (X_k read through get(k)).
 template <typename T, typename Get>
@@ -258,7 +288,7 @@ template <typename T>
 __device__ __forceinline__ T dct3_sample(const cplx<T> *Zf, int j, int logN, const RadixPlan &rp) {
     const int N = 1 << logN, M = N >> 1, logM = logN - 1;
     const int q = (j & 1) ? (N - 1 - (j >> 1)) : (j >> 1);
-    const cplx<T> z = Zf[dif_pos(q >> 1, rp, logM)];
+    const cplx<T> z = Zf[fft_slot<T>(dif_pos(q >> 1, rp, logM))];
     // conj(z) / M: real part for even q, imaginary part (of the conjugate) for odd q
     return (q & 1) ? (-z.im / T(M)) : (z.re / T(M));
 }
@@ -270,8 +300,8 @@ template <typename T>
 __device__ __forceinline__ T dst1_post(const cplx<T> *Zh, int l, int logNn, const RadixPlan &rp,
                                        const cplx<T> *__restrict__ tw, int logNtw) {
     const int Nn = 1 << logNn;
-    const cplx<T> a = Zh[dif_pos(l, rp, logNn)];
-    const cplx<T> b = cconj(Zh[dif_pos(Nn - l, rp, logNn)]);
+    const cplx<T> a = Zh[fft_slot<T>(dif_pos(l, rp, logNn))];
+    const cplx<T> b = cconj(Zh[fft_slot<T>(dif_pos(Nn - l, rp, logNn))]);
     const cplx<T> E = cscale(cadd(a, b), T(0.5));
     const cplx<T> O = cdiv2i(csub(a, b));
     const cplx<T> w = tw[l << (logNtw - logNn - 1)];   // exp(-2 pi i l / 2Nn)

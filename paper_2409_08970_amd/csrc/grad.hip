@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(256) k_grad_final(PlanTables t, const double *
     const int logT = logn + 2;
     for (int k = tid; k < n / 2; k += nthr) {
         auto get = [&](int kk) -> double { return sdv[kk]; };
-        Z[k] = dct3_pack<double>(get, k, logn, t.tw64, logT);
+        Z[fft_slot<double>(k)] = dct3_pack<double>(get, k, logn, t.tw64, logT);
     }
     __syncthreads();
     const RadixPlan rp = radix_plan(logn - 1, 1, nthr);

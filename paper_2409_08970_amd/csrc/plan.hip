@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(kPlanThreads) k_z(PlanTables t, const double *
     __shared__ int scan_tot;
     const int n = t.n, logn = t.logn, tid = threadIdx.x, nthr = blockDim.x;
     const int M = n / 2, logT = logn + 2;
-    for (int m = tid; m < M; m += nthr) buf[m] = dct2_pack<double>(v, m, n);
+    for (int m = tid; m < M; m += nthr) buf[fft_slot<double>(m)] = dct2_pack<double>(v, m, n);
     __syncthreads();
     const RadixPlan rp = radix_plan(logn - 1, 1, nthr);
     fft_dif(buf, 1, M, logn - 1, t.tw64, logT, rp);
