@@ -45,8 +45,9 @@ struct PlanTables {
     double *rowB;       // [n]    per bin: a z_0 / mu
     int32_t *m0;        // [n]    per bin: first grid tap
     double *win;        // [n * width] per bin window weights (0 for empty bins)
-    double *wina;       // [n * kTaps] per bin: rowA times the window weight at grid point
-                        //   2b + 1 - width/2 + k (taps aligned to a closed-form origin; 0 for empty bins)
+    double *wina;       // [kTaps * n] tap-major: entry (k, b) is rowA_b times the window weight at
+                        //   grid point 2b + 1 - width/2 + k (taps aligned to a closed-form origin;
+                        //   0 for empty bins)
     double *direct;     // [ndirect * n] exact rows a_i z_j / (mu_i - lambda_j)
     int32_t *direct_row;// [ndirect] output row of each direct slot
     int32_t *rowOfBin;  // [n]    output row of the NUFFT root in bin b, or -1

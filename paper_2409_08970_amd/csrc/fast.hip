@@ -235,24 +235,31 @@ __global__ void __launch_bounds__(fast_threads(LOGN)) k_fast_fwd(PlanTables t, c
     }
     __syncthreads();
 
-    // 6. outputs.  NUFFT rows in bin order: the per-bin tables are read directly (an
-    //    empty bin has zero weights and an in-range first tap), only the store needs
-    //    the row; then the deflated rows and the exact rows.
+    // 6. outputs.  NUFFT rows in bin order.  A thread takes one bin for a group of the
+    //    workgroup's signals (every kGroups-th one), so a bin's weights are read once per
+    //    group rather than once per signal, and the tap-major table makes those reads
+    //    coalesced across a wave's bins.  Then the deflated rows and the exact rows.
     const int hw = w / 2;
-    for (int g = tid; g < ns * (n - 1); g += nthr) {
-        const int s = g / (n - 1), b = g % (n - 1);
+    constexpr int kGroups = nthr / n > 1 ? nthr / n : 1;
+    for (int g = tid; g < kGroups * (n - 1); g += nthr) {
+        const int sg = g / (n - 1), b = g % (n - 1);
         const int row = t.rowOfBin[b];
+        if (row < 0) continue;   // empty bin
+        double W[kTaps];
+#pragma unroll
+        for (int k = 0; k < kTaps; ++k) W[k] = t.wina[(size_t)k * n + b];
+        const double rb = t.rowB[b];
         // aligned taps start at grid point 2b + 1 - hw (closed form: no table lookup in the
         // address); the row factor rowA is folded into the weights
         int gi = kExt + 2 * b + 1 - hw;                // index >= kExt + 1 - hw > 0
         asm volatile("" : "+v"(gi));
-        const double *Gt = big + (size_t)s * BD + gi;
-        const double *W = t.wina + (size_t)b * kTaps;
-        double acc = 0.0;
+        for (int s = sg; s < ns; s += kGroups) {
+            const double *Gt = big + (size_t)s * BD + gi;
+            double acc = 0.0;
 #pragma unroll
-        for (int k = 0; k < kTaps; ++k) acc += W[k] * Gt[k];   // fixed count: every load in flight
-        const double val = acc + t.rowB[b] * (double)sd[(size_t)s * n];
-        if (row >= 0) y[(s0 + s) * n + row] = (TIO)val;
+            for (int k = 0; k < kTaps; ++k) acc += W[k] * Gt[k];   // fixed count: every load in flight
+            y[(s0 + s) * n + row] = (TIO)(acc + rb * (double)sd[(size_t)s * n]);
+        }
     }
     for (int g = tid; g < ns * n; g += nthr) {
         const int s = g / n, k = g % n;
@@ -330,51 +337,65 @@ __global__ void __launch_bounds__(fast_threads(LOGN)) k_fast_adj(PlanTables t, c
     // point's bins do not depend on one another; the fold terms G(-p) and G(4n - p)
     // are nonzero only within hw of the two ends.
     const int hw = w / 2;
-    auto gather = [&](int s, int P) -> double {
+    constexpr int kReach = kTaps / 2 + 1;   // bins that reach one grid point, at most
+    // the bins reaching grid point P and their weights, the same for every signal: a
+    // fixed count of unconditional loads at clamped (valid) indices, the bins past the
+    // last one given weight 0
+    auto reach = [&](int P, int *bb, double *c) {
         int blo = ((P - hw - 3) >> 1) + 1;   // bins with 0 <= P - (2b + 1 - hw) < w + 2
         int bhi = (P - 1 + hw) >> 1;
         if (blo < 0) blo = 0;
         if (bhi > n - 2) bhi = n - 2;
         asm volatile("" : "+v"(blo));        // keep the first bin whole (no negative part in the base)
-        double acc = 0.0;
-        // at most kTaps / 2 + 1 bins reach a grid point: a fixed count of unconditional
-        // loads at clamped (valid) indices, the bins past bhi masked out by a select
 #pragma unroll
-        for (int k = 0; k < kTaps / 2 + 1; ++k) {
+        for (int k = 0; k < kReach; ++k) {
             const int b = blo + k;
             const bool ok = b <= bhi;
-            int bb = ok ? b : blo;
-            bb = bb < n - 1 ? bb : n - 1;             // tables have n rows (row n - 1 is zero)
-            int tap = P - 2 * bb - 1 + hw;
+            int q = ok ? b : blo;
+            q = q < n - 1 ? q : n - 1;       // tables have n rows (row n - 1 is zero)
+            int tap = P - 2 * q - 1 + hw;
             tap = tap < 0 ? 0 : (tap > kTaps - 1 ? kTaps - 1 : tap);
-            const double c = t.wina[(size_t)bb * kTaps + tap] * (double)yb[(size_t)s * n + bb];
-            acc += ok ? c : 0.0;
+            bb[k] = q;
+            c[k] = ok ? t.wina[(size_t)tap * n + q] : 0.0;
         }
+    };
+    auto spread = [&](const int *bb, const double *c, int s) -> double {
+        const TD *ys = yb + (size_t)s * n;
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < kReach; ++k) acc += c[k] * (double)ys[bb[k]];
         return acc;
     };
-    // two grid points per thread and iteration, so that the loads of both are in flight together
-    for (int g0 = tid; g0 < ns * 2 * n; g0 += 2 * nthr) {
-        double Gv[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int g = g0 + h * nthr;
-            const int s = g / (2 * n), p = g % (2 * n);
-            Gv[h] = (g < ns * 2 * n && p != 0) ? gather(s, p) : 0.0;
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int g = g0 + h * nthr;
-            if (g >= ns * 2 * n) break;
-            const int s = g / (2 * n), p = g % (2 * n);
-            double *q = big + (size_t)s * BD;
-            if (p == 0) {
+    // a thread takes one grid point for a group of the signals (every kGroups-th one)
+    constexpr int kGroups = nthr / (2 * n) > 1 ? nthr / (2 * n) : 1;
+    for (int g = tid; g < kGroups * 2 * n; g += nthr) {
+        const int sg = g / (2 * n), p = g % (2 * n);
+        if (p == 0) {
+            for (int s = sg; s < ns; s += kGroups) {
+                double *q = big + (size_t)s * BD;
                 q[0] = 0.0;
                 q[dslot(2 * n)] = 0.0;
-                continue;
             }
-            double G = Gv[h];
-            if (p <= hw) G -= gather(s, -p);
-            if (p >= 2 * n - hw) G -= gather(s, 4 * n - p);
+            continue;
+        }
+        int bb[kReach];
+        double c[kReach];
+        reach(p, bb, c);
+        for (int s = sg; s < ns; s += kGroups) {
+            double G = spread(bb, c, s);
+            if (p <= hw || p >= 2 * n - hw) {
+                int bf[kReach];
+                double cf[kReach];
+                if (p <= hw) {
+                    reach(-p, bf, cf);
+                    G -= spread(bf, cf, s);
+                }
+                if (p >= 2 * n - hw) {
+                    reach(4 * n - p, bf, cf);
+                    G -= spread(bf, cf, s);
+                }
+            }
+            double *q = big + (size_t)s * BD;
             q[dslot(p)] = G;
             q[dslot(4 * n - p)] = -G;
         }

@@ -270,7 +270,7 @@ __global__ void __launch_bounds__(kPlanThreads) k_rows(PlanTables t, const int32
         t.rowB[i] = 0.0;
         t.m0[i] = 2 * i + 1 - w / 2;
         for (int q = 0; q < w; ++q) t.win[(size_t)i * w + q] = 0.0;
-        for (int k = 0; k < kTaps; ++k) t.wina[(size_t)i * kTaps + k] = 0.0;
+        for (int k = 0; k < kTaps; ++k) t.wina[(size_t)k * n + i] = 0.0;
     }
     __syncthreads();
 
@@ -330,7 +330,7 @@ __global__ void __launch_bounds__(kPlanThreads) k_rows(PlanTables t, const int32
                 for (int q = 0; q < w; ++q) t.win[(size_t)b * w + q] = es_window(x - (m0 + q), w, beta);
                 for (int k = 0; k < w + 2; ++k) {
                     const int q = k - sh;
-                    t.wina[(size_t)b * kTaps + k] =
+                    t.wina[(size_t)k * n + b] =
                         (q >= 0 && q < w) ? t.rowA[b] * es_window(x - (m0 + q), w, beta) : 0.0;
                 }
                 t.kind[row] = ROW_NUFFT;
