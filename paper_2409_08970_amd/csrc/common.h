@@ -15,6 +15,7 @@ constexpr int kMaxLogN = 14;            // n <= 16384
 constexpr int kMaxDirect = 512;         // rows summed exactly on the FAST route
 constexpr int kMaxWidth = 16;           // NUFFT window taps
 constexpr int kTaps = kMaxWidth + 2;    // stride of the aligned window table (taps past width + 2 are 0)
+constexpr int kReach = kTaps / 2 + 1;   // bins whose window reaches one grid point, at most
 constexpr int kMaxRank = 64;            // rank-one updates of a rank-k plan
 
 template <typename T>
@@ -48,6 +49,9 @@ struct PlanTables {
     double *wina;       // [kTaps * n] tap-major: entry (k, b) is rowA_b times the window weight at
                         //   grid point 2b + 1 - width/2 + k (taps aligned to a closed-form origin;
                         //   0 for empty bins)
+    double *wspr;       // [kReach * 2n] the transposed interpolation per grid point P: entry (k, P)
+                        //   is the weight of bin blo(P) + k, blo(P) = max(0, ((P - w/2 - 3) >> 1) + 1),
+                        //   with the odd-extension folds of P near 0 and 2n merged in
     double *direct;     // [ndirect * n] exact rows a_i z_j / (mu_i - lambda_j)
     int32_t *direct_row;// [ndirect] output row of each direct slot
     int32_t *rowOfBin;  // [n]    output row of the NUFFT root in bin b, or -1

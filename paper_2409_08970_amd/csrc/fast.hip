@@ -333,71 +333,36 @@ __global__ void __launch_bounds__(fast_threads(LOGN)) k_fast_adj(PlanTables t, c
     // transpose of the interpolation: spread u_b = rowA_b y_row(b) onto the grid in
     // gather form, folded back onto G'_1..G'_{2n-1}, then written as the odd extension
     // of length 4n for the grid DST-I.  Bin b reaches grid points 2b + 1 - hw + k,
-    // k < w + 2, through the aligned weights (rowA folded in), so the loads of a grid
-    // point's bins do not depend on one another; the fold terms G(-p) and G(4n - p)
-    // are nonzero only within hw of the two ends.
+    // k < w + 2; grid point p is reached by the kReach bins from blo(p) on, whose
+    // weights (rowA and the folds G(-p), G(4n - p) near the two ends included) the
+    // plan tabulates per grid point.  A thread takes one grid point for a group of the
+    // signals (every kGroups-th one) and reads its weights once for all of them.
     const int hw = w / 2;
-    constexpr int kReach = kTaps / 2 + 1;   // bins that reach one grid point, at most
-    // the bins reaching grid point P and their weights, the same for every signal: a
-    // fixed count of unconditional loads at clamped (valid) indices, the bins past the
-    // last one given weight 0
-    auto reach = [&](int P, int *bb, double *c) {
-        int blo = ((P - hw - 3) >> 1) + 1;   // bins with 0 <= P - (2b + 1 - hw) < w + 2
-        int bhi = (P - 1 + hw) >> 1;
-        if (blo < 0) blo = 0;
-        if (bhi > n - 2) bhi = n - 2;
-        asm volatile("" : "+v"(blo));        // keep the first bin whole (no negative part in the base)
-#pragma unroll
-        for (int k = 0; k < kReach; ++k) {
-            const int b = blo + k;
-            const bool ok = b <= bhi;
-            int q = ok ? b : blo;
-            q = q < n - 1 ? q : n - 1;       // tables have n rows (row n - 1 is zero)
-            int tap = P - 2 * q - 1 + hw;
-            tap = tap < 0 ? 0 : (tap > kTaps - 1 ? kTaps - 1 : tap);
-            bb[k] = q;
-            c[k] = ok ? t.wina[(size_t)tap * n + q] : 0.0;
-        }
-    };
-    auto spread = [&](const int *bb, const double *c, int s) -> double {
-        const TD *ys = yb + (size_t)s * n;
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < kReach; ++k) acc += c[k] * (double)ys[bb[k]];
-        return acc;
-    };
-    // a thread takes one grid point for a group of the signals (every kGroups-th one)
     constexpr int kGroups = nthr / (2 * n) > 1 ? nthr / (2 * n) : 1;
     for (int g = tid; g < kGroups * 2 * n; g += nthr) {
         const int sg = g / (2 * n), p = g % (2 * n);
-        if (p == 0) {
-            for (int s = sg; s < ns; s += kGroups) {
-                double *q = big + (size_t)s * BD;
-                q[0] = 0.0;
-                q[dslot(2 * n)] = 0.0;
-            }
-            continue;
-        }
-        int bb[kReach];
+        int blo = ((p - hw - 3) >> 1) + 1;     // first bin reaching p
+        blo = blo < 0 ? 0 : blo;
+        asm volatile("" : "+v"(blo));          // keep the first bin whole (no negative part in the base)
         double c[kReach];
-        reach(p, bb, c);
+#pragma unroll
+        for (int k = 0; k < kReach; ++k) c[k] = t.wspr[(size_t)k * 2 * n + p];
         for (int s = sg; s < ns; s += kGroups) {
-            double G = spread(bb, c, s);
-            if (p <= hw || p >= 2 * n - hw) {
-                int bf[kReach];
-                double cf[kReach];
-                if (p <= hw) {
-                    reach(-p, bf, cf);
-                    G -= spread(bf, cf, s);
-                }
-                if (p >= 2 * n - hw) {
-                    reach(4 * n - p, bf, cf);
-                    G -= spread(bf, cf, s);
-                }
+            const TD *ys = yb + (size_t)s * n;
+            double G = 0.0;
+#pragma unroll
+            for (int k = 0; k < kReach; ++k) {
+                const int b = blo + k < n - 1 ? blo + k : n - 1;   // row n - 1 is zero
+                G += c[k] * (double)ys[b];
             }
             double *q = big + (size_t)s * BD;
-            q[dslot(p)] = G;
-            q[dslot(4 * n - p)] = -G;
+            if (p == 0) {
+                q[0] = 0.0;
+                q[dslot(2 * n)] = 0.0;
+            } else {
+                q[dslot(p)] = G;
+                q[dslot(4 * n - p)] = -G;
+            }
         }
     }
     if (wps > 1) {

@@ -429,6 +429,45 @@ __global__ void k_deconv(PlanTables t) {
     }
 }
 
+// The adjoint's spreading in gather form, tabulated per grid point.  Grid point P
+// collects the bins whose aligned window reaches it; the odd extension of the grid
+// folds the points -P (for P <= w/2) and 4n - P (for P >= 2n - w/2) back onto P with
+// a minus sign.  Every such bin lies in the kReach bins from blo(P) on, so one table
+// row per tap slot k holds the combined weight of bin blo(P) + k (zero past the last
+// bin); a fold bin outside that window would be a construction error (status bit 4).
+__global__ void k_spread(PlanTables t) {
+    const int n = t.n, w = t.width, hw = w / 2;
+    auto blo_of = [&](int Q) {
+        const int b = ((Q - hw - 3) >> 1) + 1;   // bins with 0 <= Q - (2b + 1 - hw) < w + 2
+        return b < 0 ? 0 : b;
+    };
+    for (int P = blockIdx.x * blockDim.x + threadIdx.x; P < 2 * n; P += gridDim.x * blockDim.x) {
+        double c[kReach];
+        for (int k = 0; k < kReach; ++k) c[k] = 0.0;
+        const int base = blo_of(P);
+        auto add = [&](int Q, double sign) {
+            const int blo = blo_of(Q);
+            int bhi = (Q - 1 + hw) >> 1;
+            if (bhi > n - 2) bhi = n - 2;
+            for (int b = blo; b <= bhi; ++b) {
+                const int k = b - base;
+                const int tap = Q - 2 * b - 1 + hw;
+                if (k < 0 || k >= kReach || tap < 0 || tap >= kTaps) {
+                    atomicOr(&t.status[0], 4);
+                    continue;
+                }
+                c[k] += sign * t.wina[(size_t)tap * n + b];
+            }
+        };
+        if (P > 0) {
+            add(P, 1.0);
+            if (P <= hw) add(-P, -1.0);
+            if (P >= 2 * n - hw) add(4 * n - P, -1.0);
+        }
+        for (int k = 0; k < kReach; ++k) t.wspr[(size_t)k * 2 * n + P] = c[k];
+    }
+}
+
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
@@ -459,7 +498,7 @@ dctplus_status plan_alloc(dctplus_plan_s *p, PlanScratch &sc, hipStream_t s) {
         {(void **)&t.z, nd}, {(void **)&t.zraw, nd}, {(void **)&t.mu, nd}, {(void **)&t.a, nd}, {(void **)&t.origin, ni},
         {(void **)&t.tau, nd}, {(void **)&t.kind, ni}, {(void **)&t.ref, ni}, {(void **)&t.hz, nd},
         {(void **)&t.deconv, nd}, {(void **)&t.rowA, nd}, {(void **)&t.rowB, nd}, {(void **)&t.m0, ni},
-        {(void **)&t.win, nd * w}, {(void **)&t.wina, nd * kTaps}, {(void **)&t.direct_row, sizeof(int32_t) * kMaxDirect},
+        {(void **)&t.win, nd * w}, {(void **)&t.wina, nd * kTaps}, {(void **)&t.wspr, nd * 2 * kReach}, {(void **)&t.direct_row, sizeof(int32_t) * kMaxDirect},
         {(void **)&t.tw64, sizeof(cplx<double>) * 4 * n}, {(void **)&t.tw32, sizeof(cplx<float>) * 4 * n},
         {(void **)&t.sintab, sizeof(double) * (2 * n + 1)}, {(void **)&t.status, sizeof(int32_t) * 8},
         {(void **)&rowOfBin, ni}, {(void **)&rowOfK, ni},
@@ -519,6 +558,7 @@ dctplus_status plan_build(dctplus_plan_s *p, const double *v_host, hipStream_t s
                        (const double *)misc, (const int32_t *)r_o, (const double *)r_tau, (const double *)r_a,
                        p->direct_kappa, rowOfBin, rowOfK);
     hipLaunchKernelGGL(k_deconv, dim3((n + 255) / 256), dim3(256), 0, s, t);
+    hipLaunchKernelGGL(k_spread, dim3((2 * n + 255) / 256), dim3(256), 0, s, t);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "plan kernels");
 
     int32_t st[8];
@@ -527,6 +567,7 @@ dctplus_status plan_build(dctplus_plan_s *p, const double *v_host, hipStream_t s
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "plan synchronize");
     if (st[0] & 1) return fail(DCTPLUS_ENOCONV, "secular solver did not converge");
     if (st[0] & 2) return fail(DCTPLUS_EDEVICE, "internal error: eigenvalue ordering is not a permutation");
+    if (st[0] & 4) return fail(DCTPLUS_EDEVICE, "internal error: spreading table out of its window");
     t.nj = st[1];
     t.ndefl = st[2];
     t.ndirect = st[3];
