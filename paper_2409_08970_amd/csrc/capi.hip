@@ -255,10 +255,12 @@ static dctplus_status plan_create(int64_t n, int32_t k, const double *rhos, cons
         if (route == DCTPLUS_ROUTE_AUTO) route = DCTPLUS_ROUTE_DENSE;
     }
     if (route == DCTPLUS_ROUTE_AUTO) {
-        // measured on MI355X (forward + adjoint, FP32): the O(n^2) MFMA/GEMM product wins up
-        // to n = 1024, the O(n log n) route from n = 4096 on.  FP64 plans stay on the dense
-        // product, which is exact to 1e-12 (the FAST route to ~1e-11, its window error)
-        route = (n >= 4096 && o.dtype == DCTPLUS_F32) ? DCTPLUS_ROUTE_FAST : DCTPLUS_ROUTE_DENSE;
+        // measured on MI355X (forward + adjoint, FP32, 256 to 16,384 signals): the O(n^2)
+        // MFMA product wins up to n = 512 at every batch and at n = 1024 from 4,096
+        // signals on; the O(n log n) route wins from n = 2048 on at every batch (1.2-1.8x
+        // at n = 2048, 1.9-2.7x at n = 4096).  FP64 plans stay on the dense product, which
+        // is exact to 1e-12 (the FAST route to ~1e-11, its window error)
+        route = (n >= 2048 && o.dtype == DCTPLUS_F32) ? DCTPLUS_ROUTE_FAST : DCTPLUS_ROUTE_DENSE;
     }
     if ((o.dtype == DCTPLUS_BF16 || o.dtype == DCTPLUS_F32_SPLIT) && route == DCTPLUS_ROUTE_FAST)
         return fail(DCTPLUS_EUNSUPPORTED, "BF16 operands apply to the DENSE and GFT routes");

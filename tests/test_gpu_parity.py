@@ -207,12 +207,12 @@ def test_double_eigenvalues_from_mirror_edge(route, n):
     p.close()
 
 
-@pytest.mark.parametrize("n,dtype,expect", [(64, "f32", "dense"), (1024, "f32", "dense"), (4096, "f32", "fast"),
-                                            (16384, "f32", "fast"), (4096, "f64", "dense"), (16384, "bf16", None),
-                                            (64, "f64", "dense")])
+@pytest.mark.parametrize("n,dtype,expect", [(64, "f32", "dense"), (1024, "f32", "dense"), (2048, "f32", "fast"),
+                                            (4096, "f32", "fast"), (16384, "f32", "fast"), (4096, "f64", "dense"),
+                                            (16384, "bf16", None), (64, "f64", "dense")])
 def test_auto_route_choice(n, dtype, expect):
     """AUTO takes the route measured faster on this GPU for FP32 signals: the dense
-    product up to n = 2048, the O(n log n) route from n = 4096.  FP64 plans keep the
+    product up to n = 1024, the O(n log n) route from n = 2048.  FP64 plans keep the
     dense product (1e-12); BF16 operands exist on the dense route only, n in {32, 64}."""
     _torch()
     from paper_2409_08970_amd import Plan, _binding as B
