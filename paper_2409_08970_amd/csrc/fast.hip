@@ -29,6 +29,8 @@
 // address formed below the start of the LDS window (a negative index folded
 // into the instruction's offset field) is not a legal address on the device,
 // even when address plus offset is.
+#include <type_traits>
+
 #include "fft.h"
 
 namespace dctplus {
@@ -80,7 +82,7 @@ __device__ __forceinline__ double grid_fold(const double *Gb, int p, int n) {
 }
 
 template <int LOGN, typename TIO, typename TD, bool kLds>
-__global__ void __launch_bounds__(fast_threads(LOGN)) k_fast_fwd(PlanTables t, const TIO *__restrict__ x, TIO *__restrict__ y,
+__global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t, const TIO *__restrict__ x, TIO *__restrict__ y,
                                                    int64_t batch, int nsig, double *__restrict__ gscratch) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int n = 1 << LOGN, logn = LOGN, nthr = fast_threads(LOGN), BD = big_doubles(n);
@@ -241,26 +243,35 @@ __global__ void __launch_bounds__(fast_threads(LOGN)) k_fast_fwd(PlanTables t, c
     //    coalesced across a wave's bins.  Then the deflated rows and the exact rows.
     const int hw = w / 2;
     constexpr int kGroups = nthr / n > 1 ? nthr / n : 1;
-    for (int g = tid; g < kGroups * (n - 1); g += nthr) {
-        const int sg = g / (n - 1), b = g % (n - 1);
-        const int row = t.rowOfBin[b];
-        if (row < 0) continue;   // empty bin
-        double W[kTaps];
+    // NT taps per bin (fixed count: every load in flight); taps past w + 2 are zero, so
+    // the default FP32 width 12 reads 14 and every other width all kTaps
+    auto interpolate = [&](auto nt) {
+        constexpr int NT = decltype(nt)::value;
+        for (int g = tid; g < kGroups * (n - 1); g += nthr) {
+            const int sg = g / (n - 1), b = g % (n - 1);
+            const int row = t.rowOfBin[b];
+            if (row < 0) continue;   // empty bin
+            double W[NT];
 #pragma unroll
-        for (int k = 0; k < kTaps; ++k) W[k] = t.wina[(size_t)k * n + b];
-        const double rb = t.rowB[b];
-        // aligned taps start at grid point 2b + 1 - hw (closed form: no table lookup in the
-        // address); the row factor rowA is folded into the weights
-        int gi = kExt + 2 * b + 1 - hw;                // index >= kExt + 1 - hw > 0
-        asm volatile("" : "+v"(gi));
-        for (int s = sg; s < ns; s += kGroups) {
-            const double *Gt = big + (size_t)s * BD + gi;
-            double acc = 0.0;
+            for (int k = 0; k < NT; ++k) W[k] = t.wina[(size_t)k * n + b];
+            const double rb = t.rowB[b];
+            // aligned taps start at grid point 2b + 1 - hw (closed form: no table lookup in
+            // the address); the row factor rowA is folded into the weights
+            int gi = kExt + 2 * b + 1 - hw;                // index >= kExt + 1 - hw > 0
+            asm volatile("" : "+v"(gi));
+            for (int s = sg; s < ns; s += kGroups) {
+                const double *Gt = big + (size_t)s * BD + gi;
+                double acc = 0.0;
 #pragma unroll
-            for (int k = 0; k < kTaps; ++k) acc += W[k] * Gt[k];   // fixed count: every load in flight
-            y[(s0 + s) * n + row] = (TIO)(acc + rb * (double)sd[(size_t)s * n]);
+                for (int k = 0; k < NT; ++k) acc += W[k] * Gt[k];
+                y[(s0 + s) * n + row] = (TIO)(acc + rb * (double)sd[(size_t)s * n]);
+            }
         }
-    }
+    };
+    if (w == 12)
+        interpolate(std::integral_constant<int, 14>{});
+    else
+        interpolate(std::integral_constant<int, kTaps>{});
     for (int g = tid; g < ns * n; g += nthr) {
         const int s = g / n, k = g % n;
         const int row = t.rowOfK[k];
@@ -273,7 +284,7 @@ __global__ void __launch_bounds__(fast_threads(LOGN)) k_fast_fwd(PlanTables t, c
 }
 
 template <int LOGN, typename TIO, typename TD, bool kLds>
-__global__ void __launch_bounds__(fast_threads(LOGN)) k_fast_adj(PlanTables t, const TIO *__restrict__ y, TIO *__restrict__ x,
+__global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_adj(PlanTables t, const TIO *__restrict__ y, TIO *__restrict__ x,
                                                    int64_t batch, int nsig, double *__restrict__ gscratch) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int n = 1 << LOGN, logn = LOGN, nthr = fast_threads(LOGN), BD = big_doubles(n);
@@ -339,32 +350,41 @@ __global__ void __launch_bounds__(fast_threads(LOGN)) k_fast_adj(PlanTables t, c
     // signals (every kGroups-th one) and reads its weights once for all of them.
     const int hw = w / 2;
     constexpr int kGroups = nthr / (2 * n) > 1 ? nthr / (2 * n) : 1;
-    for (int g = tid; g < kGroups * 2 * n; g += nthr) {
-        const int sg = g / (2 * n), p = g % (2 * n);
-        int blo = ((p - hw - 3) >> 1) + 1;     // first bin reaching p
-        blo = blo < 0 ? 0 : blo;
-        asm volatile("" : "+v"(blo));          // keep the first bin whole (no negative part in the base)
-        double c[kReach];
+    // NR bins per grid point: the table is zero past the w / 2 + 2 that reach one at
+    // width w, so the default FP32 width 12 reads 8 and every other width all kReach
+    auto spread = [&](auto nr) {
+        constexpr int NR = decltype(nr)::value;
+        for (int g = tid; g < kGroups * 2 * n; g += nthr) {
+            const int sg = g / (2 * n), p = g % (2 * n);
+            int blo = ((p - hw - 3) >> 1) + 1;     // first bin reaching p
+            blo = blo < 0 ? 0 : blo;
+            asm volatile("" : "+v"(blo));          // keep the first bin whole (no negative part in the base)
+            double c[NR];
 #pragma unroll
-        for (int k = 0; k < kReach; ++k) c[k] = t.wspr[(size_t)k * 2 * n + p];
-        for (int s = sg; s < ns; s += kGroups) {
-            const TD *ys = yb + (size_t)s * n;
-            double G = 0.0;
+            for (int k = 0; k < NR; ++k) c[k] = t.wspr[(size_t)k * 2 * n + p];
+            for (int s = sg; s < ns; s += kGroups) {
+                const TD *ys = yb + (size_t)s * n;
+                double G = 0.0;
 #pragma unroll
-            for (int k = 0; k < kReach; ++k) {
-                const int b = blo + k < n - 1 ? blo + k : n - 1;   // row n - 1 is zero
-                G += c[k] * (double)ys[b];
-            }
-            double *q = big + (size_t)s * BD;
-            if (p == 0) {
-                q[0] = 0.0;
-                q[dslot(2 * n)] = 0.0;
-            } else {
-                q[dslot(p)] = G;
-                q[dslot(4 * n - p)] = -G;
+                for (int k = 0; k < NR; ++k) {
+                    const int b = blo + k < n - 1 ? blo + k : n - 1;   // row n - 1 is zero
+                    G += c[k] * (double)ys[b];
+                }
+                double *q = big + (size_t)s * BD;
+                if (p == 0) {
+                    q[0] = 0.0;
+                    q[dslot(2 * n)] = 0.0;
+                } else {
+                    q[dslot(p)] = G;
+                    q[dslot(4 * n - p)] = -G;
+                }
             }
         }
-    }
+    };
+    if (w == 12)
+        spread(std::integral_constant<int, 8>{});
+    else
+        spread(std::integral_constant<int, kReach>{});
     if (wps > 1) {
         __syncthreads();
         for (int s = tid; s < ns; s += nthr) {
