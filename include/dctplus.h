@@ -72,9 +72,11 @@ typedef enum {
     DCTPLUS_F64 = 1,  /* FP64 signals and FP64 arithmetic throughout (dense routes: FP64 MFMA
                          product with the FP64 X^T, 8 n^2 bytes) */
     DCTPLUS_BF16 = 2, /* FP32 signals; dense routes only: BF16 MFMA operands, FP32 accumulation */
-    DCTPLUS_F32_SPLIT = 3 /* FP32 signals; dense routes, n in {32, 64}: both operands split into three
-                             BF16 pieces, the six cross products of order <= 2^-16 accumulated in FP32
-                             on MFMA (FP32-level accuracy); arrays 16-byte aligned */
+    DCTPLUS_F32_SPLIT = 3 /* FP32 signals; dense routes, 32 <= n <= 4096 (the factored form: n = 64):
+                             both operands split into three BF16 pieces, the six cross products of
+                             order >= 2^-16 accumulated in FP32 on MFMA (FP32-level accuracy); arrays
+                             16-byte aligned.  Above n = 64 the plan keeps the three pieces of its
+                             factor for each direction (12 n^2 bytes besides the FP32 factor) */
 } dctplus_dtype;
 
 /* How the product with diag(a) C(mu, lambda) diag(z) is formed. */

@@ -264,8 +264,8 @@ static dctplus_status plan_create(int64_t n, int32_t k, const double *rhos, cons
     }
     if ((o.dtype == DCTPLUS_BF16 || o.dtype == DCTPLUS_F32_SPLIT) && route == DCTPLUS_ROUTE_FAST)
         return fail(DCTPLUS_EUNSUPPORTED, "BF16 operands apply to the DENSE and GFT routes");
-    if (o.dtype == DCTPLUS_F32_SPLIT && (n < 32 || n > 64))
-        return fail(DCTPLUS_EUNSUPPORTED, "the split-BF16 mode supports n in {32, 64}");
+    if (o.dtype == DCTPLUS_F32_SPLIT && (n < 32 || n > 4096))
+        return fail(DCTPLUS_EUNSUPPORTED, "the split-BF16 mode supports 32 <= n <= 4096");
     if (o.dtype == DCTPLUS_F32_SPLIT && o.factored == 1 && n != 64)
         return fail(DCTPLUS_EUNSUPPORTED, "the factored split-BF16 form supports n = 64");
 
@@ -348,8 +348,10 @@ dctplus_status dctplus_plan_general(int64_t n, const double *lambda_host, const 
     if (o.route == DCTPLUS_ROUTE_FAST || o.factored)
         return fail(DCTPLUS_EUNSUPPORTED, "a general base has no fast transform here: its plans apply the dense "
                                           "product with X^T (DENSE, GFT or AUTO, not factored)");
-    if ((o.dtype == DCTPLUS_BF16 || o.dtype == DCTPLUS_F32_SPLIT) && (n < 32 || n > 64))
+    if (o.dtype == DCTPLUS_BF16 && (n < 32 || n > 64))
         return fail(DCTPLUS_EUNSUPPORTED, "BF16 operands support n in {32, 64}");
+    if (o.dtype == DCTPLUS_F32_SPLIT && (n < 32 || n > 4096))
+        return fail(DCTPLUS_EUNSUPPORTED, "the split-BF16 mode supports 32 <= n <= 4096");
     if (!(o.defl_tol > 0.0)) o.defl_tol = 1e-13;
     int dev = o.device;
     hipError_t e;

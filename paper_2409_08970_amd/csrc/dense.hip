@@ -26,6 +26,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
 typedef float f2v __attribute__((ext_vector_type(2)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
     // round to nearest even (finite inputs)
@@ -990,6 +991,150 @@ __global__ void __launch_bounds__(256) k_gemm32(const float *__restrict__ A, con
             }
 }
 
+// ---------------------------------------------------------------------------
+// The split-BF16 dense product for n > 64 (FP32 accuracy from BF16 MFMA): C = A B
+// with B(k, j) = S[j][k], S given as the three pieces (h, m, l) of the plan's
+// three-piece split, each an n x n BF16 matrix with the contraction index
+// contiguous.  A (the signals, FP32) is staged through LDS and split on the fly,
+// per MFMA fragment; the six cross products of order >= 2^-16 (hl, lh, mm, mh,
+// hm, hh, smallest first) accumulate in FP32.  BM x BN tiles, a K step of 32 (one
+// v_mfma_f32_16x16x32_bf16), four waves in a 2 x 2 grid; the next step's operands
+// are fetched into registers while the current one is multiplied.
+// ---------------------------------------------------------------------------
+constexpr int SKB = 32;          // contraction step
+constexpr int SPA = SKB + 4;     // A row stride in LDS (floats)
+constexpr int SPB = SKB + 8;     // B row stride in LDS (bf16)
+
+template <int BM, int BN>
+__global__ void __launch_bounds__(256) k_gemm_split(const float *__restrict__ A, const uint16_t *__restrict__ S,
+                                                    float *__restrict__ C, int64_t M, int n) {
+    constexpr int WM = BM / 2, WN = BN / 2;          // per-wave tile
+    constexpr int TM = WM / 16, TN = WN / 16;        // MFMA tiles per wave
+    constexpr int AV = BM * SKB / 4 / 256;           // float4 of A per thread and step
+    constexpr int BV = BN * SKB / 8 / 256;           // 8-BF16 chunks of one piece per thread and step
+    static_assert(AV >= 1 && BV >= 1, "tile too small for 256 threads");
+    __shared__ __align__(16) float As[BM * SPA];
+    __shared__ __align__(16) uint16_t Bs[3 * BN * SPB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l16 = lane & 15, g = lane >> 4;
+    const int64_t m0 = (int64_t)blockIdx.y * BM;
+    const int j0 = blockIdx.x * BN;
+    const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+    const size_t nn = (size_t)n * n;
+    f4 acc[TM][TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    f4 ra[AV];
+    u4v rh[BV], rm[BV], rl[BV];   // the three pieces of the B step
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < AV; ++u) {
+            const int q = tid + 256 * u, r = q / (SKB / 4), c = q % (SKB / 4);
+            const int64_t row = m0 + r;
+            ra[u] = row < M ? *reinterpret_cast<const f4 *>(A + row * n + k0 + 4 * c) : f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int u = 0; u < BV; ++u) {
+            const int q = tid + 256 * u, r = q / (SKB / 8), c = q % (SKB / 8);
+            const uint16_t *src = S + (size_t)(j0 + r) * n + k0 + 8 * c;
+            rh[u] = *reinterpret_cast<const u4v *>(src);
+            rm[u] = *reinterpret_cast<const u4v *>(src + nn);
+            rl[u] = *reinterpret_cast<const u4v *>(src + 2 * nn);
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int u = 0; u < AV; ++u) {
+            const int q = tid + 256 * u, r = q / (SKB / 4), c = q % (SKB / 4);
+            *reinterpret_cast<f4 *>(As + r * SPA + 4 * c) = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < BV; ++u) {
+            const int q = tid + 256 * u, r = q / (SKB / 8), c = q % (SKB / 8);
+            *reinterpret_cast<u4v *>(Bs + (0 * BN + r) * SPB + 8 * c) = rh[u];
+            *reinterpret_cast<u4v *>(Bs + (1 * BN + r) * SPB + 8 * c) = rm[u];
+            *reinterpret_cast<u4v *>(Bs + (2 * BN + r) * SPB + 8 * c) = rl[u];
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < n; k0 += SKB) {
+        __syncthreads();                       // the previous step's operands are consumed
+        stash();
+        __syncthreads();
+        if (k0 + SKB < n) fetch(k0 + SKB);     // in flight while this step is multiplied
+        // A fragments of this wave (lane: row l16 of the tile, contraction 8 g .. 8 g + 7),
+        // split into three BF16 pieces with the hardware conversion (round to nearest even)
+        bf8 ah[TM], am[TM], al[TM];
+#pragma unroll
+        for (int a = 0; a < TM; ++a) {
+            const float *src = As + (wm + 16 * a + l16) * SPA + 8 * g;
+            const f4 x0 = *reinterpret_cast<const f4 *>(src), x1 = *reinterpret_cast<const f4 *>(src + 4);
+#pragma unroll
+            for (int e = 0; e < 8; e += 2) {
+                const f4 &xs = e < 4 ? x0 : x1;
+                const f2v x = (e & 2) ? f2v{xs.z, xs.w} : f2v{xs.x, xs.y};
+                const bf2v h = __builtin_convertvector(x, bf2v);
+                const f2v r = x - __builtin_convertvector(h, f2v);
+                const bf2v m = __builtin_convertvector(r, bf2v);
+                const bf2v l = __builtin_convertvector(r - __builtin_convertvector(m, f2v), bf2v);
+                ah[a][e] = h[0];
+                ah[a][e + 1] = h[1];
+                am[a][e] = m[0];
+                am[a][e + 1] = m[1];
+                al[a][e] = l[0];
+                al[a][e + 1] = l[1];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+            const int rowb = wn + 16 * b + l16;
+            const bf8 bh = *reinterpret_cast<const bf8 *>(Bs + (0 * BN + rowb) * SPB + 8 * g);
+            const bf8 bm = *reinterpret_cast<const bf8 *>(Bs + (1 * BN + rowb) * SPB + 8 * g);
+            const bf8 bl = *reinterpret_cast<const bf8 *>(Bs + (2 * BN + rowb) * SPB + 8 * g);
+#pragma unroll
+            for (int a = 0; a < TM; ++a) {
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl, acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh, acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[a], bm, acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[a], bh, acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bm, acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh, acc[a][b], 0, 0, 0);
+            }
+        }
+    }
+    // element v of lane (l16, g) is row 4 g + v (signal), column l16 (output)
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = m0 + wm + 16 * a + 4 * g + v;
+                if (row < M) C[row * n + j0 + wn + 16 * b + l16] = acc[a][b][v];
+            }
+}
+
+// The split images of a folded plan with n > 64: direction d (0 forward, 1 adjoint)
+// holds S_d[j][k] = P[j][k] (forward, y = P x) or P[k][j] (adjoint, x = P^T y) as three
+// BF16 pieces, [d][piece][n][n].
+__global__ void k_split_image(const float *__restrict__ P, int n, uint16_t *__restrict__ img) {
+    const size_t nn = (size_t)n * n;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < 2 * nn; e += (size_t)gridDim.x * blockDim.x) {
+        const int d = (int)(e / nn);
+        const size_t f = e - (size_t)d * nn;
+        const int j = (int)(f / n), k = (int)(f % n);
+        const float v = d == 0 ? P[(size_t)j * n + k] : P[(size_t)k * n + j];
+        uint16_t h, m, l;
+        split3(v, h, m, l);
+        uint16_t *base = img + (size_t)d * 3 * nn;
+        base[f] = h;
+        base[nn + f] = m;
+        base[2 * nn + f] = l;
+    }
+}
+
 int num_cus() {
     static int ncu = 0;
     if (ncu == 0) {
@@ -1052,6 +1197,19 @@ void launch_gemm32(const float *A, const float *P, float *C, int64_t M, int n, b
     }
 }
 
+// The split-BF16 product for n > 64: tiles as launch_gemm32 (cfg 1 / 2 force 64 / 128).
+void launch_gemm_split(const float *A, const uint16_t *S, float *C, int64_t M, int n, int cfg, hipStream_t s) {
+    const int64_t big = ((M + 127) / 128) * (n / 128);
+    const bool t128 = n % 128 == 0 && (cfg == 2 || (cfg == 0 && big >= 2 * num_cus()));
+    if (t128) {
+        const dim3 grid((unsigned)(n / 128), (unsigned)((M + 127) / 128));
+        hipLaunchKernelGGL((k_gemm_split<128, 128>), grid, dim3(256), 0, s, A, S, C, M, n);
+    } else {
+        const dim3 grid((unsigned)(n / 64), (unsigned)((M + 63) / 64));
+        hipLaunchKernelGGL((k_gemm_split<64, 64>), grid, dim3(256), 0, s, A, S, C, M, n);
+    }
+}
+
 template <int N, bool BF>
 void launch_small(const dctplus_plan_s *p, const float *in, float *out, int64_t batch, int adj, int pre,
                   hipStream_t s) {
@@ -1105,8 +1263,28 @@ dctplus_status build_factored_image(dctplus_plan_s *p, hipStream_t s) {
     return DCTPLUS_OK;
 }
 
+dctplus_status build_split_images(dctplus_plan_s *p, hipStream_t s) {
+    const int n = (int)p->n;
+    const size_t bytes = sizeof(uint16_t) * 3 * (size_t)n * n;   // one direction
+    hipError_t e = hipMalloc(&p->simg, 2 * bytes);
+    if (e != hipSuccess) {
+        p->simg = nullptr;
+        (void)hipGetLastError();
+        return fail(DCTPLUS_ENOMEM, "hipMalloc for the split-BF16 operand images failed");
+    }
+    p->simg_bytes = bytes;
+    const size_t total = 2 * (size_t)n * n;
+    const unsigned blocks = (unsigned)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
+    hipLaunchKernelGGL(k_split_image, dim3(blocks), dim3(256), 0, s, (const float *)p->t.mt32, n,
+                       (uint16_t *)p->simg);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "split-BF16 operand images");
+    return DCTPLUS_OK;
+}
+
 dctplus_status stream_images(dctplus_plan_s *p, hipStream_t s) {
     const int n = (int)p->n;
+    if (p->t.folded && n > 64 && p->dtype == DCTPLUS_F32_SPLIT) return build_split_images(p, s);
     if (!p->t.folded && n == 64) {
         if (p->dtype == DCTPLUS_F32_SPLIT) return build_factored_image<2>(p, s);
         if (p->dtype == DCTPLUS_F32) return build_factored_image<0>(p, s);
@@ -1293,7 +1471,14 @@ dctplus_status dense_apply(dctplus_plan_s *p, const void *inv, void *outv, int64
         const int nsig = n >= 4096 ? 1 : 4096 / n;
         const size_t lds = sizeof(cplx<float>) * (size_t)nsig * (n / 2);
         const dim3 dgrid((unsigned)((batch + nsig - 1) / nsig));
-        if (!adjoint) {
+        if (split) {
+            // folded plans only (the factored split form is n = 64); float4 loads of the signals
+            if (pre || !p->simg) return fail(DCTPLUS_EDEVICE, "no split-BF16 operand images on this plan");
+            if (((uintptr_t)in & 15) != 0)
+                return fail(DCTPLUS_EUNSUPPORTED, "the split-BF16 mode needs 16-byte aligned arrays");
+            const uint16_t *S = (const uint16_t *)((const unsigned char *)p->simg + (adj ? p->simg_bytes : 0));
+            launch_gemm_split(in, S, out, batch, n, cfg, s);    // y_b = P x_b, or x_b = P^T y_b
+        } else if (!adjoint) {
             const float *A = in;
             if (pre) {
                 hipLaunchKernelGGL(k_dct_rows, dgrid, dim3(256), lds, s, p->t, in, tmp, batch, 0, nsig);

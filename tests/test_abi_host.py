@@ -82,7 +82,8 @@ def test_plan_rejects_bad_options_on_host(lib):
     assert B.dctplus_plan(128, 1.0, np.ones(128), o, check=False)[0] == B.DCTPLUS_EUNSUPPORTED
     o = B.dctplus_default_opts()
     o.dtype = B.DCTPLUS_F32_SPLIT
-    assert B.dctplus_plan(128, 1.0, np.ones(128), o, check=False)[0] == B.DCTPLUS_EUNSUPPORTED
+    assert B.dctplus_plan(8192, 1.0, np.ones(8192), o, check=False)[0] == B.DCTPLUS_EUNSUPPORTED
+    assert B.dctplus_plan(16, 1.0, np.ones(16), o, check=False)[0] == B.DCTPLUS_EUNSUPPORTED
     o = B.dctplus_default_opts()
     o.dtype = B.DCTPLUS_BF16
     o.route = B.DCTPLUS_ROUTE_FAST

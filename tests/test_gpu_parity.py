@@ -378,6 +378,40 @@ def test_f32_split_bf16_products(route, n, kind):
     p.close()
 
 
+@pytest.mark.parametrize("route", ["dense", "gft"])
+@pytest.mark.parametrize("n,batch", [(128, 333), (256, 333), (1024, 130), (4096, 40)])
+@pytest.mark.parametrize("kind", ["dense", "edge", "negative"])
+def test_f32_split_gemm(route, n, batch, kind):
+    """The split-BF16 product above n = 64 (64 x 64 tiles at these batches, a ragged
+    last tile): FP32 bar, with tiny and huge signals keeping their relative accuracy."""
+    rho, v = case(n, kind)
+    x = workloads.ar1(np.random.default_rng(5), batch, n, 0.95)
+    x[5] *= 1e-30
+    x[6] *= 1e30
+    fwd, adj = reference(n, rho, v)
+    p = make_plan(n, rho, v, route, dtype="f32split")
+    assert relerr(run(p, x), fwd(x.astype(np.float64))) <= TOL32, (route, n, kind)
+    assert relerr(run(p, x, adjoint=True), adj(x.astype(np.float64))) <= TOL32, (route, n, kind)
+    p.close()
+
+
+@pytest.mark.parametrize("n,batch", [(256, 32768), (1024, 8192)])
+def test_f32_split_gemm_large_tiles(n, batch):
+    """Batches that take the 128 x 128 tiles of the split-BF16 product; sampled rows
+    against the oracle (every row of the last, ragged tile included)."""
+    torch = _torch()
+    rho, v = case(n, "dense")
+    x = workloads.ar1(np.random.default_rng(6), batch - 37, n, 0.95)
+    fwd, adj = reference(n, rho, v)
+    p = make_plan(n, rho, v, "dense", dtype="f32split")
+    y = run(p, x)
+    xa = run(p, x, adjoint=True)
+    rows = np.r_[np.arange(0, x.shape[0], 97), np.arange(x.shape[0] - 150, x.shape[0])]
+    assert relerr(y[rows], fwd(x[rows].astype(np.float64))) <= TOL32
+    assert relerr(xa[rows], adj(x[rows].astype(np.float64))) <= TOL32
+    p.close()
+
+
 @pytest.mark.parametrize("kind", ["dense", "loop0", "loopn", "edge", "negative"])
 def test_factored_split_n64(kind):
     """The factored form at n = 64 with split-BF16 products (DCT-II in registers, then
