@@ -188,36 +188,43 @@ def bench_selection(torch, dev, steps, warmup):
 def bench_gradient(torch, dev, steps, warmup):
     """Gradient workload: n = 256, 65,536 N(0,1) signals, rho = 1, random unit v,
     loss = mean |y|.  A step = forward + gradient (dl/dx via the adjoint, dl/drho
-    and dl/dv via the batch Gram matrix), inputs resident in HBM."""
+    and dl/dv via the batch Gram matrix), inputs resident in HBM.  Timed for an FP32
+    plan (FP32 MFMA products) and a split-BF16 plan (FP32-accurate BF16 products)."""
     import workloads
     from paper_2409_08970_amd import Plan
     W = workloads.workload5()
     n, batch = W["n"], W["x"].shape[0]
     x = torch.from_numpy(W["x"]).to(dev)
-    pl = Plan(n, W["rho"], W["v"], route="auto")
     y = torch.empty_like(x)
 
-    def step():
-        pl.forward(x, out=y)
-        gy = torch.sign(y) / y.numel()
-        pl.grad(y, gy)
+    def timed(pl):
+        def step():
+            pl.forward(x, out=y)
+            gy = torch.sign(y) / y.numel()
+            pl.grad(y, gy)
 
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    a, b = _events(torch)
-    reps = max(5, steps)
-    a.record()
-    for _ in range(reps):
-        step()
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / reps
-    pl.close()
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        a, b = _events(torch)
+        reps = max(5, steps)
+        a.record()
+        for _ in range(reps):
+            step()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        pl.close()
+        return ms
+
+    ms = timed(Plan(n, W["rho"], W["v"], route="auto"))
+    ms_split = timed(Plan(n, W["rho"], W["v"], route="dense", dtype="f32split"))
     return {"workload": f"n={n}, {batch} N(0,1) signals, rho={W['rho']}, random unit v, loss mean|y|",
             "ms_per_step": ms, "signal_samples_per_s": batch * n / (ms * 1e-3),
             "step": "forward + dl/dx (adjoint) + dl/drho, dl/dv (Gram matrix G = sum gy y^T, 2 B n^2 flops)",
-            "gram_tflops_if_alone": 2.0 * batch * n * n / (ms * 1e-3) / 1e12}
+            "gram_tflops_if_alone": 2.0 * batch * n * n / (ms * 1e-3) / 1e12,
+            "f32split": {"ms_per_step": ms_split, "signal_samples_per_s": batch * n / (ms_split * 1e-3),
+                         "products": "forward and dl/dx on the split-BF16 product (FP32 accuracy)"}}
 
 
 def main():
@@ -353,6 +360,27 @@ def main():
             p32.close()
         comp["n32_workload"] = n32
         del x32, y32, r32
+        # a mid-size graph: n = 1024, 8,192 N(0,1) signals (the O(n log n) route against the
+        # dense products in FP32 and split-BF16 arithmetic)
+        W3 = workloads.workload3(1024, "dense", batch=8192)
+        x3 = torch.from_numpy(W3["x"]).to(dev)
+        y3 = torch.empty_like(x3)
+        r3 = torch.empty_like(x3)
+        mid = {}
+        for name, kw in (("fast", dict(route="fast")), ("dense", dict(route="dense")),
+                         ("dense_f32split", dict(route="dense", dtype="f32split"))):
+            pm = Plan(1024, W3["rho"], W3["v"], **kw)
+            tm = time_pair(torch, lambda: pm.forward(x3, out=y3), lambda: pm.adjoint(y3, out=r3),
+                           max(20, args.steps), 2)
+            mid[name] = {"ms_per_step": tm[0], "value": 8192 * 1024 / (tm[0] * 1e-3)}
+            pm.close()
+        A = torch.randn(1024, 1024, device=dev)
+        At = A.t().contiguous()
+        tm = time_pair(torch, lambda: torch.matmul(x3, A, out=y3), lambda: torch.matmul(y3, At, out=r3),
+                       max(3, args.steps // 4), 2)[0]
+        mid["gft_torch_matmul"] = {"ms_per_step": tm, "value": 8192 * 1024 / (tm * 1e-3)}
+        comp["n1024_workload"] = mid
+        del A, At, x3, y3, r3
         # large graphs: 256 N(0,1) signals, dense unit v, rho = 0.5
         for nl in (4096, 16384):
             W3 = workloads.workload3(nl, "dense")
@@ -380,6 +408,13 @@ def main():
                                         "[grid DST] + 2 (w+2) n [window gather, w=12], fp64 except the DCT; "
                                         "peak = FP64 vector 78.6 TFLOP/s (FP32 counted against it too)"}
                 p3.close()
+            if nl <= 4096:
+                # the split-BF16 dense product (FP32 accuracy; plans up to n = 4096)
+                ps = Plan(nl, W3["rho"], W3["v"], route="dense", dtype="f32split")
+                t3 = time_pair(torch, lambda: ps.forward(x3, out=y3), lambda: ps.adjoint(y3, out=r3),
+                               max(20, args.steps), 2)
+                large["dense_f32split"] = {"ms_per_step": t3[0], "value": 256 * nl / (t3[0] * 1e-3)}
+                ps.close()
             pa = Plan(nl, W3["rho"], W3["v"], route="auto")
             large["dct_plus_auto"] = {"route": pa.route, **large[pa.route]}
             pa.close()

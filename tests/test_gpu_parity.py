@@ -618,7 +618,7 @@ def _oracle_basis(n, rho, v):
     return plan["mu"], X
 
 
-def _grad_case(n, rho, v, x, route, rows=None):
+def _grad_case(n, rho, v, x, route, rows=None, dtype="f32"):
     """GPU (y, dx, drho, dv) and oracle (dx, drho, dv) for loss = mean |y|.
 
     rows: indices of the signals whose dl/dx is compared (all when None)."""
@@ -627,7 +627,7 @@ def _grad_case(n, rho, v, x, route, rows=None):
     y_ref = oracle.forward(X, x.astype(np.float64))
     gy32 = oracle.loss_l1_grad(y_ref).astype(np.float32)
     gy = gy32.astype(np.float64)
-    p = make_plan(n, rho, v, route)
+    p = make_plan(n, rho, v, route, dtype=dtype)
     xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
     y = p.forward(xt)
     gx, grho, gv = p.grad(y, torch.from_numpy(gy32).cuda())
@@ -721,6 +721,27 @@ def test_gradient_workload5_full_batch():
     gpu, ref = _grad_case(n, rho, v, x, "auto", rows=rows)
     e = _check_grad(gpu, ref)
     print(f"workload 5 gradient: d rho rel err {e[0]:.2e}, d v rel err {e[1]:.2e}")
+
+
+@pytest.mark.parametrize("n,kind", [(256, "dense"), (256, "negative"), (1024, "edge")])
+def test_gradient_split_products_vs_oracle(n, kind):
+    """Gradients of a split-BF16 plan (forward and dl/dx on the split product): the FP32 bars."""
+    rho, v = _grad_kind(n, kind)
+    batch = 1024 if n <= 256 else 256
+    x = np.random.default_rng(9 + n).standard_normal((batch, n)).astype(np.float32)
+    gpu, ref = _grad_case(n, rho, v, x, "dense", dtype="f32split")
+    _check_grad(gpu, ref)
+
+
+def test_gradient_workload5_full_batch_split():
+    """The full gradient workload on a split-BF16 plan (128 x 128 tiles of the split product)."""
+    n = 256
+    W = workloads.workload5()
+    rho, v, x = W["rho"], W["v"], W["x"]
+    rows = np.sort(np.random.default_rng(4).choice(x.shape[0], 512, replace=False))
+    gpu, ref = _grad_case(n, rho, v, x, "dense", rows=rows, dtype="f32split")
+    e = _check_grad(gpu, ref)
+    print(f"workload 5 gradient, split products: d rho rel err {e[0]:.2e}, d v rel err {e[1]:.2e}")
 
 
 def test_gradient_double_eigenvalue_is_refused():
