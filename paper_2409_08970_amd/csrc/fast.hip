@@ -118,27 +118,32 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t
     __syncthreads();
     constexpr RadixPlan rpA = radix_plan(logn - 1, kPlanSig, nthr);
     fft_dif(Zf, ns, strideZ, logn - 1, twd, logT, rpA);
+    // 2. the DCT's outputs X_k, X_{n-k} (thread of k), and with them the four values of
+    //    the odd extension u (length 2n) of h = hz * s_d that they give: u(q) at double
+    //    n + q of the signal's buffer, i.e. n complex points from double n on (under the
+    //    bank swizzle).  The DCT's own FFT data (doubles [0, n)) is not overwritten.
+    const int strideB = BD / 2;   // complex doubles per signal
+    cplx<double> *Bc = reinterpret_cast<cplx<double> *>(big);
     for (int g = tid; g < ns * (n / 2 + 1); g += nthr) {
         const int s = g / (n / 2 + 1), k = g % (n / 2 + 1);
         TD Xk, XNk;
         dct2_post(Zf + (size_t)s * strideZ, k, logn, rpA, twd, logT, Xk, XNk);
         sd[(size_t)s * n + k] = Xk;
-        if (k > 0 && k < n / 2) sd[(size_t)s * n + n - k] = XNk;
-    }
-    __syncthreads();
-
-    // 2. h and its odd extension u (length 2n), packed as n complex points at doubles [n, 3n)
-    const int strideB = BD / 2;   // complex doubles per signal
-    cplx<double> *Bc = reinterpret_cast<cplx<double> *>(big);
-    for (int g = tid; g < ns * n; g += nthr) {
-        const int s = g / n, m = g % n;
-        const TD *sds = sd + (size_t)s * n;
-        auto u = [&](int q) -> double {
-            if (q == 0 || q == n) return 0.0;
-            if (q < n) return t.hz[q] * (double)sds[q];
-            return -t.hz[2 * n - q] * (double)sds[2 * n - q];
-        };
-        Bc[(size_t)s * strideB + n / 2 + fft_slot<double>(m)] = {u(2 * m), u(2 * m + 1)};
+        double *ub = big + (size_t)s * BD + n;
+        if (k == 0) {
+            ub[dslot(0)] = 0.0;
+            ub[dslot(n)] = 0.0;
+        } else {
+            const double uk = t.hz[k] * (double)Xk;
+            ub[dslot(k)] = uk;
+            ub[dslot(2 * n - k)] = -uk;
+            if (k < n / 2) {
+                sd[(size_t)s * n + n - k] = XNk;
+                const double unk = t.hz[n - k] * (double)XNk;
+                ub[dslot(n - k)] = unk;
+                ub[dslot(n + k)] = -unk;
+            }
+        }
     }
     __syncthreads();
     constexpr RadixPlan rpB = radix_plan(logn, kPlanSig, nthr);
@@ -146,11 +151,18 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t
 
     // 3. c = DST-I(h), times the window deconvolution; written as the odd
     //    extension q (length 4n, zero for n <= l <= 3n) in doubles [0, n) and (3n, 4n)
+    // The grid FFT's input is zero on its middle half (doubles [n, 3n]): when its first
+    // pass has radix >= 4 that pass leaves those points out, and only double 3n, which
+    // shares a complex point with the last c, is written here; otherwise the middle is
+    // cleared.
+    constexpr RadixPlan rpC = radix_plan(logn + 1, kPlanSig, nthr);
+    constexpr bool kPruned = rpC.lr(0) >= 2;
     for (int g = tid; g < ns * n; g += nthr) {
         const int s = g / n, l = g % n;
         double *q = big + (size_t)s * BD;
         if (l == 0) {
             q[0] = 0.0;
+            if (kPruned) q[dslot(3 * n)] = 0.0;
             continue;
         }
         const double c = dst1_post(Bc + (size_t)s * strideB + n / 2, l, logn, rpB, t.tw64, logT) * t.deconv[l];
@@ -158,15 +170,16 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t
         q[dslot(4 * n - l)] = -c;
     }
     __syncthreads();
-    for (int g = tid; g < ns * (2 * n + 1); g += nthr) {
-        const int s = g / (2 * n + 1), p = g % (2 * n + 1);
-        big[(size_t)s * BD + dslot(n + p)] = 0.0;
+    if (!kPruned) {
+        for (int g = tid; g < ns * (2 * n + 1); g += nthr) {
+            const int s = g / (2 * n + 1), p = g % (2 * n + 1);
+            big[(size_t)s * BD + dslot(n + p)] = 0.0;
+        }
+        __syncthreads();
     }
-    __syncthreads();
 
     // 4. grid G_m = sum_l chat_l sin(pi l m / 2n), m = 0..2n (DST-I of length 2n)
-    constexpr RadixPlan rpC = radix_plan(logn + 1, kPlanSig, nthr);
-    fft_dif(Bc, ns, strideB, logn + 1, t.tw64, logT, rpC);
+    fft_dif(Bc, ns, strideB, logn + 1, t.tw64, logT, rpC, kPruned);
     // pairs (m, 2n - m), m = 1..n, staged in registers (the output overwrites the FFT data)
     double gv[2 * kRounds];
 #pragma unroll

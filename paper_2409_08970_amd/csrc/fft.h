@@ -143,7 +143,10 @@ __device__ __forceinline__ int fft_slot(int e) {
     return e ^ (h & ((1 << B) - 1));
 }
 
-template <int LR, typename T>
+// ZMID: the first pass of a transform whose input is zero on its middle half
+// (points [N/4, 3N/4)); with radix R >= 4 those are the butterfly inputs
+// r in [R/4, 3R/4), which are taken as zero instead of read.
+template <int LR, typename T, bool ZMID = false>
 __device__ __forceinline__ void fft_pass(cplx<T> *buf, int nsig, int stride, int logN, int logL,
                                          const cplx<T> *__restrict__ tw, int logNtw, int tid, int nthr) {
     constexpr int R = 1 << LR;
@@ -165,7 +168,12 @@ __device__ __forceinline__ void fft_pass(cplx<T> *buf, int nsig, int stride, int
         const int a = fft_slot<T>((sub << logL) + j);
         cplx<T> x[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) x[r] = sig[a ^ roff[r]];
+        for (int r = 0; r < R; ++r) {
+            if (ZMID && R >= 4 && r >= R / 4 && r < 3 * R / 4)
+                x[r] = cplx<T>{T(0), T(0)};
+            else
+                x[r] = sig[a ^ roff[r]];
+        }
         dft_reg<LR>(x);
         if (logm > 0) {
             // twiddles w^r, w = exp(-2 pi i j / L): w, w^4 and w^8 come from the table and
@@ -206,18 +214,28 @@ __device__ __forceinline__ void fft_pass(cplx<T> *buf, int nsig, int stride, int
 
 // In-place forward FFT (exp(-2 pi i j k / N)).  The caller must barrier
 // before (input written) and may read the output right after return.
+// zero_mid: the input is zero on points [N/4, 3N/4) and the plan's first radix is at
+// least 4; the first pass then reads only the other half (the caller need not clear it).
 template <typename T>
 __device__ __forceinline__ void fft_dif(cplx<T> *buf, int nsig, int stride, int logN, const cplx<T> *__restrict__ tw,
-                        int logNtw, const RadixPlan &rp) {
+                        int logNtw, const RadixPlan &rp, bool zero_mid = false) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     int logL = logN;
     for (int i = 0; i < rp.np; ++i) {
         const int lr = rp.lr(i);
-        switch (lr) {
-            case 1: fft_pass<1, T>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
-            case 2: fft_pass<2, T>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
-            case 3: fft_pass<3, T>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
-            default: fft_pass<4, T>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
+        if (i == 0 && zero_mid) {
+            switch (lr) {
+                case 2: fft_pass<2, T, true>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
+                case 3: fft_pass<3, T, true>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
+                default: fft_pass<4, T, true>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
+            }
+        } else {
+            switch (lr) {
+                case 1: fft_pass<1, T>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
+                case 2: fft_pass<2, T>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
+                case 3: fft_pass<3, T>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
+                default: fft_pass<4, T>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
+            }
         }
         logL -= lr;
         __syncthreads();

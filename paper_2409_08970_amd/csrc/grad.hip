@@ -110,6 +110,9 @@ __global__ void __launch_bounds__(256) k_gram_sum(const float *__restrict__ part
     const int64_t nn = (int64_t)n * n;
     if (e >= nn) return;
     double g = 0.0;
+    // unrolled so that the loads of eight partials are in flight together; the additions
+    // keep their order
+#pragma unroll 8
     for (int sp = 0; sp < nsplit; ++sp) g += (double)partial[(size_t)sp * nn + e];
     const int i = (int)(e / n), k = (int)(e % n);
     G[e] = g;
