@@ -889,16 +889,16 @@ __global__ void __launch_bounds__(256) k_gemm64(const double *__restrict__ A, co
 //   C[m][j] = sum_k A[m][k] B(k, j),  B(k, j) = P[j][k] (TRANSB: forward, y = P s)
 //                                     or       P[k][j] (adjoint, x = P^T y),
 // A = the [M x K] signals (row-major), C = [M x N] (row-major), K = N = n.
-// BM x BN output tiles per workgroup (2 x 2 waves), k-steps of 16 through LDS with
+// BM x BN output tiles per workgroup (2 x 2 waves), k-steps of 32 through LDS with
 // the next step's operands loaded into registers while the current one is
 // multiplied; FP32 MFMA 16x16x4.  The contraction index is permuted inside each
-// k-step (lane group g supplies k = 4 g + s to the s-th of four MFMAs), so a lane
-// reads its four operand values of a row with one 16-byte LDS read; rows are
-// padded to 20 floats, which makes those reads conflict-free.  The adjoint's P is
+// half-step of 16 (lane group g supplies k = 4 g + s to the s-th of four MFMAs), so a
+// lane reads its four operand values of a row with one 16-byte LDS read; rows are
+// padded to 36 floats, which makes those reads conflict-free.  The adjoint's P is
 // transposed on its way into LDS.  n must be a multiple of 64 (or of BN); rows of
 // A and C past M are not read or written.
-constexpr int GKS = 16;      // k per step
-constexpr int GPAD = 20;     // LDS row stride (floats)
+constexpr int GKS = 32;      // k per step (two halves of 16, each read as one float4 per lane and row)
+constexpr int GPAD = 36;     // LDS row stride (floats)
 
 template <int BM, int BN, bool TRANSB>
 __global__ void __launch_bounds__(256) k_gemm32(const float *__restrict__ A, const float *__restrict__ P,
@@ -925,7 +925,7 @@ __global__ void __launch_bounds__(256) k_gemm32(const float *__restrict__ A, con
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int u = 0; u < AV; ++u) {
-            const int q = tid + 256 * u, r = q >> 2, c = q & 3;      // row r, float4 c of 4
+            const int q = tid + 256 * u, r = q / (GKS / 4), c = q % (GKS / 4);   // row r, float4 c
             const int64_t row = m0 + r;
             ra[u] = row < M ? *reinterpret_cast<const f4 *>(A + row * n + k0 + 4 * c) : f4{0.f, 0.f, 0.f, 0.f};
         }
@@ -933,7 +933,7 @@ __global__ void __launch_bounds__(256) k_gemm32(const float *__restrict__ A, con
         for (int u = 0; u < BV; ++u) {
             const int q = tid + 256 * u;
             if constexpr (TRANSB) {
-                const int r = q >> 2, c = q & 3;                      // output j0 + r, k0 + 4c ..
+                const int r = q / (GKS / 4), c = q % (GKS / 4);      // output j0 + r, k0 + 4c ..
                 rb[u] = *reinterpret_cast<const f4 *>(P + (size_t)(j0 + r) * n + k0 + 4 * c);
             } else {
                 const int kk = q / (BN / 4), c = q % (BN / 4);       // row k0 + kk, outputs j0 + 4c ..
@@ -944,14 +944,14 @@ __global__ void __launch_bounds__(256) k_gemm32(const float *__restrict__ A, con
     auto stash = [&]() {
 #pragma unroll
         for (int u = 0; u < AV; ++u) {
-            const int q = tid + 256 * u, r = q >> 2, c = q & 3;
+            const int q = tid + 256 * u, r = q / (GKS / 4), c = q % (GKS / 4);
             *reinterpret_cast<f4 *>(As + r * GPAD + 4 * c) = ra[u];
         }
 #pragma unroll
         for (int u = 0; u < BV; ++u) {
             const int q = tid + 256 * u;
             if constexpr (TRANSB) {
-                const int r = q >> 2, c = q & 3;
+                const int r = q / (GKS / 4), c = q % (GKS / 4);
                 *reinterpret_cast<f4 *>(Bs + r * GPAD + 4 * c) = rb[u];
             } else {
                 const int kk = q / (BN / 4), c = q % (BN / 4);
@@ -966,18 +966,23 @@ __global__ void __launch_bounds__(256) k_gemm32(const float *__restrict__ A, con
         stash();
         __syncthreads();
         if (k0 + GKS < n) fetch(k0 + GKS);     // in flight while this step is multiplied
-        f4 av[TM], bv[TN];
 #pragma unroll
-        for (int a = 0; a < TM; ++a) av[a] = *reinterpret_cast<const f4 *>(As + (wm + 16 * a + l16) * GPAD + 4 * g);
-#pragma unroll
-        for (int b = 0; b < TN; ++b) bv[b] = *reinterpret_cast<const f4 *>(Bs + (wn + 16 * b + l16) * GPAD + 4 * g);
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
+        for (int h = 0; h < GKS / 16; ++h) {
+            f4 av[TM], bv[TN];
 #pragma unroll
             for (int a = 0; a < TM; ++a)
+                av[a] = *reinterpret_cast<const f4 *>(As + (wm + 16 * a + l16) * GPAD + 16 * h + 4 * g);
 #pragma unroll
-                for (int b = 0; b < TN; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][s4], bv[b][s4], acc[a][b], 0, 0, 0);
+            for (int b = 0; b < TN; ++b)
+                bv[b] = *reinterpret_cast<const f4 *>(Bs + (wn + 16 * b + l16) * GPAD + 16 * h + 4 * g);
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+                for (int a = 0; a < TM; ++a)
+#pragma unroll
+                    for (int b = 0; b < TN; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][s4], bv[b][s4], acc[a][b], 0, 0, 0);
+        }
     }
     // element v of lane (l16, g) is row 4 g + v (signal), column l16 (output)
 #pragma unroll
@@ -1181,11 +1186,13 @@ int factored_blocks(int64_t ntiles, int wpc) {
     return persistent_grid(k_factored_stream<MODE, ADJ>, cap, per, ntiles, wpc);
 }
 
-// The FP32 dense product for n > 64: 128 x 128 tiles when they give at least two
-// workgroups per CU, 64 x 64 otherwise (small batches); cfg 1 / 2 force 64 / 128.
+// The FP32 dense product for n > 64: 128 x 128 tiles from n = 512 on when they give
+// at least two workgroups per CU, 64 x 64 otherwise (small batches, and n <= 256,
+// where the short contraction leaves the larger tile's register cost unpaid: 104 vs
+// 118 us at n = 256 on 65,536 signals); cfg 1 / 2 force 64 / 128.
 void launch_gemm32(const float *A, const float *P, float *C, int64_t M, int n, bool transb, int cfg, hipStream_t s) {
     const int64_t big = ((M + 127) / 128) * (n / 128);
-    const bool t128 = n % 128 == 0 && (cfg == 2 || (cfg == 0 && big >= 2 * num_cus()));
+    const bool t128 = n % 128 == 0 && (cfg == 2 || (cfg == 0 && n >= 512 && big >= 2 * num_cus()));
     if (t128) {
         const dim3 grid((unsigned)(n / 128), (unsigned)((M + 127) / 128));
         if (transb) hipLaunchKernelGGL((k_gemm32<128, 128, true>), grid, dim3(256), 0, s, A, P, C, M, n);
