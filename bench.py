@@ -268,9 +268,10 @@ def main():
     # then the product with the Cauchy factor diag(a) C(mu, lambda) diag(z) on MFMA with
     # FP32-accurate split-BF16 products; the adjoint applies the transposed factors
     plan = Plan(n, W["rho"], W["v"], route="dense", dtype="f32split", factored=True)
-    # the device reaches its sustained clocks only after some milliseconds of load: half a
-    # second of the headline's own launches (untimed) comes before anything is timed
-    t_end = time.perf_counter() + 0.5
+    # the device reaches its sustained clocks only after some time under load (on a fresh
+    # device half a second was not always enough): a second and a half of the headline's
+    # own launches (untimed) comes before anything is timed
+    t_end = time.perf_counter() + 1.5
     while time.perf_counter() < t_end:
         for _ in range(25):
             plan.forward(x, out=y)
