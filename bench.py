@@ -237,6 +237,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline DCT+ route (for profiler passes): no comparators, no CPU baseline")
+    ap.add_argument("--fast-n", type=int, default=0,
+                    help="only the FAST route at this n on the large-graph workload (256 N(0,1) signals): "
+                         "three forward + adjoint pairs, for profiler passes; prints nothing timed")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run 3 device copies of the 256 MiB input (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -257,6 +260,19 @@ def main():
     y = torch.empty_like(x)
     xr = torch.empty_like(x)
     print(f"workload: n={n}, batch={batch}, rho={W['rho']:.4f}", file=sys.stderr, flush=True)
+    if args.fast_n:
+        W3 = workloads.workload3(args.fast_n, "dense")
+        x3 = torch.from_numpy(W3["x"]).to(dev)
+        y3 = torch.empty_like(x3)
+        r3 = torch.empty_like(x3)
+        pf = Plan(args.fast_n, W3["rho"], W3["v"], route="fast")
+        for _ in range(3):
+            pf.forward(x3, out=y3)
+            pf.adjoint(y3, out=r3)
+        torch.cuda.synchronize()
+        pf.close()
+        print(json.dumps({"fast_n": args.fast_n, "signals": x3.shape[0], "pairs": 3}), flush=True)
+        return
     if args.copy_probe:
         for _ in range(3):
             y.copy_(x)
