@@ -894,8 +894,9 @@ __global__ void __launch_bounds__(256) k_gemm64(const double *__restrict__ A, co
 // multiplied; FP32 MFMA 16x16x4.  The contraction index is permuted inside each
 // half-step of 16 (lane group g supplies k = 4 g + s to the s-th of four MFMAs), so a
 // lane reads its four operand values of a row with one 16-byte LDS read; rows are
-// padded to 36 floats, which makes those reads conflict-free.  The adjoint's P is
-// transposed on its way into LDS.  n must be a multiple of 64 (or of BN); rows of
+// padded to 36 floats, which makes those reads conflict-free.  The adjoint keeps P's
+// rows as loaded (k-major) and reads each operand value on its own.  n must be a
+// multiple of 64 (or of BN); rows of
 // A and C past M are not read or written.
 constexpr int GKS = 32;      // k per step (two halves of 16, each read as one float4 per lane and row)
 constexpr int GPAD = 36;     // LDS row stride (floats)
@@ -909,7 +910,11 @@ __global__ void __launch_bounds__(256) k_gemm32(const float *__restrict__ A, con
     constexpr int BV = BN * GKS / 4 / 256;           // float4 of B per thread and step
     static_assert(AV >= 1 && BV >= 1, "tile too small for 256 threads");
     __shared__ __align__(16) float As[BM * GPAD];
-    __shared__ __align__(16) float Bs[BN * GPAD];
+    // B in LDS: TRANSB as [output][k] rows (the layout of A); otherwise as loaded, [k][output]
+    // rows of BN + 4 floats, each MFMA operand value then one 4-byte read (lane (l16, g) of a
+    // read lands on bank l16 + 16 g: conflict-free), instead of a transposing store
+    constexpr int LDB = BN + 4;
+    __shared__ __align__(16) float Bs[TRANSB ? BN * GPAD : GKS * LDB];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, g = lane >> 4;
     const int64_t m0 = (int64_t)blockIdx.y * BM;
@@ -955,8 +960,7 @@ __global__ void __launch_bounds__(256) k_gemm32(const float *__restrict__ A, con
                 *reinterpret_cast<f4 *>(Bs + r * GPAD + 4 * c) = rb[u];
             } else {
                 const int kk = q / (BN / 4), c = q % (BN / 4);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) Bs[(4 * c + e) * GPAD + kk] = rb[u][e];
+                *reinterpret_cast<f4 *>(Bs + kk * LDB + 4 * c) = rb[u];
             }
         }
     };
@@ -973,8 +977,14 @@ __global__ void __launch_bounds__(256) k_gemm32(const float *__restrict__ A, con
             for (int a = 0; a < TM; ++a)
                 av[a] = *reinterpret_cast<const f4 *>(As + (wm + 16 * a + l16) * GPAD + 16 * h + 4 * g);
 #pragma unroll
-            for (int b = 0; b < TN; ++b)
-                bv[b] = *reinterpret_cast<const f4 *>(Bs + (wn + 16 * b + l16) * GPAD + 16 * h + 4 * g);
+            for (int b = 0; b < TN; ++b) {
+                if constexpr (TRANSB) {
+                    bv[b] = *reinterpret_cast<const f4 *>(Bs + (wn + 16 * b + l16) * GPAD + 16 * h + 4 * g);
+                } else {
+                    const float *col = Bs + (16 * h + 4 * g) * LDB + wn + 16 * b + l16;
+                    bv[b] = f4{col[0], col[LDB], col[2 * LDB], col[3 * LDB]};
+                }
+            }
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
