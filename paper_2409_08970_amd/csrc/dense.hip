@@ -792,9 +792,21 @@ __global__ void __launch_bounds__(256) k_dct_rows(PlanTables t, const float *__r
     const int ns = (int)((batch - s0) < nsig ? (batch - s0) : nsig);
     const RadixPlan rp = radix_plan(logn - 1, ns, nthr);
     if (dir == 0) {
-        for (int g = tid; g < ns * M; g += nthr) {
-            const int s = g / M, m = g % M;
-            Z[(size_t)s * M + fft_slot<float>(m)] = dct2_pack<float>(in + (s0 + s) * n, m, n);
+        if ((((uintptr_t)in) & 15) == 0) {
+            // 16-byte chunks of the rows (coalesced), two packed points each
+            for (int g = tid; g < ns * (M / 2); g += nthr) {
+                const int s = g / (M / 2), tq = g % (M / 2);
+                const float4 x4 = *reinterpret_cast<const float4 *>(in + (s0 + s) * n + 4 * tq);
+                cplx<float> zt, zr;
+                dct2_pack4(x4, zt, zr);
+                Z[(size_t)s * M + fft_slot<float>(tq)] = zt;
+                Z[(size_t)s * M + fft_slot<float>(M - 1 - tq)] = zr;
+            }
+        } else {
+            for (int g = tid; g < ns * M; g += nthr) {
+                const int s = g / M, m = g % M;
+                Z[(size_t)s * M + fft_slot<float>(m)] = dct2_pack<float>(in + (s0 + s) * n, m, n);
+            }
         }
         __syncthreads();
         fft_dif(Z, ns, M, logn - 1, t.tw32, logT, rp);

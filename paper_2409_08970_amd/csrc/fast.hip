@@ -111,9 +111,24 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t
     // 1. DCT-II of every signal (Makhoul: reorder, FFT of n/2 packed points, twiddle)
     const int strideZ = BD * (int)sizeof(double) / (int)sizeof(cplx<TD>);
     cplx<TD> *Zf = reinterpret_cast<cplx<TD> *>(big);
-    for (int g = tid; g < ns * (n / 2); g += nthr) {
-        const int s = g / (n / 2), m = g % (n / 2);
-        Zf[(size_t)s * strideZ + fft_slot<TD>(m)] = dct2_pack<TD>(x + (s0 + s) * n, m, n);
+    bool vec4 = false;   // FP32 rows read as 16-byte chunks (coalesced), two packed points each
+    if constexpr (sizeof(TIO) == 4 && sizeof(TD) == 4 && n >= 4) vec4 = (((uintptr_t)x) & 15) == 0;
+    if (vec4) {
+        if constexpr (sizeof(TIO) == 4 && sizeof(TD) == 4 && n >= 4) {
+            for (int g = tid; g < ns * (n / 4); g += nthr) {
+                const int s = g / (n / 4), tq = g % (n / 4);
+                const float4 x4 = *reinterpret_cast<const float4 *>(x + (s0 + s) * n + 4 * tq);
+                cplx<float> zt, zr;
+                dct2_pack4(x4, zt, zr);
+                Zf[(size_t)s * strideZ + fft_slot<TD>(tq)] = zt;
+                Zf[(size_t)s * strideZ + fft_slot<TD>(n / 2 - 1 - tq)] = zr;
+            }
+        }
+    } else {
+        for (int g = tid; g < ns * (n / 2); g += nthr) {
+            const int s = g / (n / 2), m = g % (n / 2);
+            Zf[(size_t)s * strideZ + fft_slot<TD>(m)] = dct2_pack<TD>(x + (s0 + s) * n, m, n);
+        }
     }
     __syncthreads();
     constexpr RadixPlan rpA = radix_plan(logn - 1, kPlanSig, nthr);

@@ -256,6 +256,14 @@ __device__ __forceinline__ cplx<T> dct2_pack(const Src *x, int m, int N) {
     return {vq(2 * m), vq(2 * m + 1)};
 }
 
+// The same packing from four consecutive samples x[4t .. 4t+3] (one 16-byte load),
+// 0 <= t < N/4: Z_t = x[4t] + i x[4t+2] and Z_{N/2-1-t} = x[4t+3] + i x[4t+1]
+// (v_{2t} = x[4t], v_{2t+1} = x[4t+2]; v_{N-2-2t} = x[4t+3], v_{N-1-2t} = x[4t+1]).
+__device__ __forceinline__ void dct2_pack4(const float4 x4, cplx<float> &zt, cplx<float> &zr) {
+    zt = {x4.x, x4.z};
+    zr = {x4.w, x4.y};
+}
+
 // Orthonormal DCT-II outputs X_k and X_{N-k} (0 <= k <= N/2) from the FFT of
 // the packed sequence (M = N/2 points, digit-reversed per rp).  For k = 0 the
 // second output is meaningless; for k = N/2 both are X_{N/2}.
