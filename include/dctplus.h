@@ -257,11 +257,15 @@ dctplus_status dctplus_plan_info(dctplus_plan_t plan, double *mu, double *a, dou
 
 /* Copy one named plan table to HOST memory (synchronous; for tests and tools).
  * name: "z", "zraw", "mu", "a", "tau", "hz", "deconv", "rowA", "rowB", "win", "direct",
- *       "sintab" (double); "origin", "kind", "ref", "m0", "rowOfBin", "rowOfK", "direct_row",
- *       "ntie" (one value: the number of secular roots tying a deflated lambda) (int32);
- *       "tune": int8 [2][64], the launch configuration dctplus_tune chose per direction
- *       (0 forward, 1 adjoint) and batch bucket floor(log2 batch), 0 = built-in.  *bytes: capacity of dst on input, size of the table on output;
- *       dst may be NULL to query the size.  Unknown name: EINVAL. */
+ *       "sintab" (double); "wina" (double [18 taps][n], tap-major: the window weight of
+ *       bin b at grid point 2b + 1 - width/2 + tap, times the bin's row factor);
+ *       "wspr" (double [10][2n]: grid point P's weight for bin blo(P) + slot, the
+ *       adjoint's spreading); "origin", "kind", "ref", "m0", "rowOfBin", "rowOfK",
+ *       "direct_row", "ntie" (one value: the number of secular roots tying a deflated
+ *       lambda) (int32); "tune": int8 [2][64], the launch configuration dctplus_tune chose
+ *       per direction (0 forward, 1 adjoint) and batch bucket floor(log2 batch), 0 = built-in.
+ * *bytes: capacity of dst on input, size of the table on output; dst may be NULL to
+ * query the size.  Unknown name: EINVAL. */
 dctplus_status dctplus_plan_table(dctplus_plan_t plan, const char *name, void *dst, int64_t *bytes);
 
 /* Release a plan and its device memory (NULL is a no-op).  Synchronises the device. */

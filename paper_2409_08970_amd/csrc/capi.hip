@@ -544,7 +544,7 @@ dctplus_status dctplus_plan_table(dctplus_plan_t p, const char *name, void *dst,
         {"z", p->t.z, 8 * n}, {"zraw", p->t.zraw, 8 * n}, {"mu", p->t.mu, 8 * n}, {"a", p->t.a, 8 * n},
         {"tau", p->t.tau, 8 * n}, {"hz", p->t.hz, 8 * n}, {"deconv", p->t.deconv, 8 * n},
         {"rowA", p->t.rowA, 8 * n}, {"rowB", p->t.rowB, 8 * n}, {"win", p->t.win, 8 * n * w},
-        {"wina", p->t.wina, 8 * n * kTaps},
+        {"wina", p->t.wina, 8 * n * kTaps}, {"wspr", p->t.wspr, 8 * 2 * n * kReach},
         {"direct", p->t.direct, 8 * n * (nd <= kMaxDirect ? nd : 0)}, {"sintab", p->t.sintab, 8 * (2 * n + 1)},
         {"origin", p->t.origin, 4 * n}, {"kind", p->t.kind, 4 * n}, {"ref", p->t.ref, 4 * n},
         {"m0", p->t.m0, 4 * n}, {"rowOfBin", p->t.rowOfBin, 4 * n}, {"rowOfK", p->t.rowOfK, 4 * n},

@@ -299,6 +299,46 @@ def test_fast_roots_past_their_origin_bin(dtype, tol):
     assert relerr(xa, oracle.semi_adjoint(n, 2.0, v, xin, sp)) <= tol
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("n", [8, 64, 1024])
+def test_fast_spreading_is_the_transpose_of_the_interpolation(dtype, n):
+    """The adjoint's spreading table (per grid point, folds merged in) against the
+    forward's window table (per bin): <u, I G> = <S u, G> for random bin values u and
+    grid values G_1..G_{2n-1}, the interpolation I reading the grid's odd extension
+    (G(-p) = -G(p), G(4n - p) = -G(p), G_0 = G_2n = 0) at 2b + 1 - w/2 + k."""
+    _torch()
+    from paper_2409_08970_amd import dctplus_plan_table
+    rho, v = case(n, "dense")
+    p = make_plan(n, rho, v, "fast", dtype=dtype)
+    w = int(p.info["counts"][2])                 # the plan's window width
+    hw = w // 2
+    taps = 18
+    wina = dctplus_plan_table(p.handle, "wina").reshape(taps, n)
+    wspr = dctplus_plan_table(p.handle, "wspr").reshape(10, 2 * n)
+    p.close()
+    g = np.random.default_rng(n)
+    u = g.standard_normal(n)
+    u[n - 1] = 0.0                               # bins are 0 .. n - 2
+    Gin = np.zeros(2 * n + 1)
+    Gin[1:2 * n] = g.standard_normal(2 * n - 1)
+
+    def grid(q):                                 # odd extension, period 4n
+        q %= 4 * n
+        return Gin[q] if q <= 2 * n else -Gin[4 * n - q]
+    lhs = 0.0
+    for b in range(n - 1):
+        t = sum(wina[k, b] * grid(2 * b + 1 - hw + k) for k in range(taps))
+        lhs += u[b] * t
+    rhs = 0.0
+    for P in range(1, 2 * n):
+        blo = max(0, ((P - hw - 3) >> 1) + 1)
+        Sp = sum(wspr[k, P] * u[min(blo + k, n - 1)] for k in range(10))
+        rhs += Sp * Gin[P]
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, np.abs(wina).sum() * np.abs(u).max() * np.abs(Gin).max())
+    # no weight past the bins that reach a grid point at this width
+    assert np.all(wspr[hw + 2:] == 0.0)
+
+
 @pytest.mark.parametrize("n", [16, 64, 256])
 def test_fast_route_exact_row_threshold(n):
     """direct_kappa bounds the NUFFT error amplification a row may have before it is
