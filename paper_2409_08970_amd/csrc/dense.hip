@@ -1143,6 +1143,16 @@ __global__ void __launch_bounds__(256) k_gemm_split(const float *__restrict__ A,
             }
 }
 
+// P^T of an FP32 plan with 64 < n <= 4096, so that the forward product reads its operand
+// tiles k-major like the adjoint (the faster load and LDS pattern of k_gemm32).
+__global__ void k_transpose32(const float *__restrict__ P, int n, float *__restrict__ PT) {
+    const size_t nn = (size_t)n * n;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (size_t)gridDim.x * blockDim.x) {
+        const int j = (int)(e / n), k = (int)(e % n);
+        PT[e] = P[(size_t)k * n + j];
+    }
+}
+
 // The split images of a folded plan with n > 64: direction d (0 forward, 1 adjoint)
 // holds S_d[j][k] = P[j][k] (forward, y = P x) or P[k][j] (adjoint, x = P^T y) as three
 // BF16 pieces, [d][piece][n][n].
@@ -1311,9 +1321,28 @@ dctplus_status build_split_images(dctplus_plan_s *p, hipStream_t s) {
     return DCTPLUS_OK;
 }
 
+dctplus_status build_transposed(dctplus_plan_s *p, hipStream_t s) {
+    const int n = (int)p->n;
+    const size_t bytes = sizeof(float) * (size_t)n * n;
+    hipError_t e = hipMalloc(&p->simg, bytes);
+    if (e != hipSuccess) {
+        p->simg = nullptr;
+        (void)hipGetLastError();
+        return fail(DCTPLUS_ENOMEM, "hipMalloc for the transposed dense factor failed");
+    }
+    p->simg_bytes = bytes;
+    const size_t total = (size_t)n * n;
+    const unsigned blocks = (unsigned)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
+    hipLaunchKernelGGL(k_transpose32, dim3(blocks), dim3(256), 0, s, (const float *)p->t.mt32, n, (float *)p->simg);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "transposed dense factor");
+    return DCTPLUS_OK;
+}
+
 dctplus_status stream_images(dctplus_plan_s *p, hipStream_t s) {
     const int n = (int)p->n;
     if (p->t.folded && n > 64 && p->dtype == DCTPLUS_F32_SPLIT) return build_split_images(p, s);
+    if (n > 64 && n <= 4096 && p->dtype == DCTPLUS_F32) return build_transposed(p, s);
     if (!p->t.folded && n == 64) {
         if (p->dtype == DCTPLUS_F32_SPLIT) return build_factored_image<2>(p, s);
         if (p->dtype == DCTPLUS_F32) return build_factored_image<0>(p, s);
@@ -1513,7 +1542,9 @@ dctplus_status dense_apply(dctplus_plan_s *p, const void *inv, void *outv, int64
                 hipLaunchKernelGGL(k_dct_rows, dgrid, dim3(256), lds, s, p->t, in, tmp, batch, 0, nsig);
                 A = tmp;
             }
-            launch_gemm32(A, p->t.mt32, out, batch, n, true, cfg, s);      // y_b = P x_b
+            // y_b = P x_b: with P^T kept (n <= 4096), the adjoint's k-major operand path
+            if (p->simg) launch_gemm32(A, (const float *)p->simg, out, batch, n, false, cfg, s);
+            else launch_gemm32(A, p->t.mt32, out, batch, n, true, cfg, s);
         } else {
             float *C = pre ? tmp : out;
             launch_gemm32(in, p->t.mt32, C, batch, n, false, cfg, s);      // x_b = P^T y_b
