@@ -68,7 +68,8 @@ typedef enum {
 
 /* Element type of signals, and the arithmetic of the bulk of the transform. */
 typedef enum {
-    DCTPLUS_F32 = 0,  /* FP32 signals; FP32 DCT, FP64 Cauchy stage (fast), FP32 MFMA (dense) */
+    DCTPLUS_F32 = 0,  /* FP32 signals; FP32 DCT, FP64 Cauchy stage (fast), FP32 MFMA (dense; for
+                         64 < n <= 4096 the plan keeps the factor and its transpose, 8 n^2 bytes) */
     DCTPLUS_F64 = 1,  /* FP64 signals and FP64 arithmetic throughout (dense routes: FP64 MFMA
                          product with the FP64 X^T, 8 n^2 bytes) */
     DCTPLUS_BF16 = 2, /* FP32 signals; dense routes only: BF16 MFMA operands, FP32 accumulation */
