@@ -96,6 +96,106 @@ __global__ void __launch_bounds__(256) k_gram(const float *__restrict__ gy, cons
             }
 }
 
+// The same partials for split-BF16 plans: each 32-row stage is one K step of
+// v_mfma_f32_16x16x32_bf16; both operands are split into three BF16 pieces per
+// fragment (hardware round-to-nearest conversions) and the six cross products of
+// order >= 2^-16 accumulate in FP32.  A lane's fragment is eight consecutive batch
+// rows of one column (rows 8 g .. 8 g + 7), read as single floats; the row stride of
+// 130 floats puts the four lane groups of a read on distinct banks.
+typedef __bf16 gbf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 gbf2 __attribute__((ext_vector_type(2)));
+typedef float gf2 __attribute__((ext_vector_type(2)));
+constexpr int GPS = GT + 2;
+
+__device__ __forceinline__ void split_frag(const float *col, int stride, gbf8 &h, gbf8 &m, gbf8 &l) {
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+        const gf2 x = {col[e * stride], col[(e + 1) * stride]};
+        const gbf2 xh = __builtin_convertvector(x, gbf2);
+        const gf2 r = x - __builtin_convertvector(xh, gf2);
+        const gbf2 xm = __builtin_convertvector(r, gbf2);
+        const gbf2 xl = __builtin_convertvector(r - __builtin_convertvector(xm, gf2), gbf2);
+        h[e] = xh[0];
+        h[e + 1] = xh[1];
+        m[e] = xm[0];
+        m[e + 1] = xm[1];
+        l[e] = xl[0];
+        l[e + 1] = xl[1];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_gram_split(const float *__restrict__ gy, const float *__restrict__ y,
+                                                    float *__restrict__ partial, int64_t batch, int n,
+                                                    int64_t rows_per) {
+    __shared__ float As[GK][GPS];   // gy rows [b][i]
+    __shared__ float Bs[GK][GPS];   // y rows  [b][k]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l16 = lane & 15, g = lane >> 4;
+    const int i0 = blockIdx.x * GT, k0 = blockIdx.y * GT, split = blockIdx.z;
+    const int64_t b0 = (int64_t)split * rows_per;
+    int64_t b1 = b0 + rows_per;
+    if (b1 > batch) b1 = batch;
+    const int wi = (wave >> 1) * 64, wk = (wave & 1) * 64;
+    f4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    // stage loader as in k_gram: thread t owns column c = t % 128 of rows t / 128 + 2u
+    float ra[16], rb[16];
+    const int c = tid & 127, r0 = tid >> 7;
+    const bool ci = i0 + c < n, ck = k0 + c < n;
+    const int64_t step = 2 * (int64_t)n;
+    auto fetch = [&](int64_t bb) {
+        const float *pa = gy + (bb + r0) * n + i0 + c;
+        const float *pb = y + (bb + r0) * n + k0 + c;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const bool rin = bb + r0 + 2 * u < b1;
+            ra[u] = (rin && ci) ? pa[u * step] : 0.0f;
+            rb[u] = (rin && ck) ? pb[u * step] : 0.0f;
+        }
+    };
+    fetch(b0);
+    for (int64_t bb = b0; bb < b1; bb += GK) {
+        __syncthreads();                            // the previous stage is consumed
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            As[r0 + 2 * u][c] = ra[u];
+            Bs[r0 + 2 * u][c] = rb[u];
+        }
+        __syncthreads();
+        if (bb + GK < b1) fetch(bb + GK);           // in flight while this stage is multiplied
+        gbf8 ah[4], am[4], al[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) split_frag(&As[8 * g][wi + 16 * a + l16], GPS, ah[a], am[a], al[a]);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            gbf8 bh, bm, bl;
+            split_frag(&Bs[8 * g][wk + 16 * b + l16], GPS, bh, bm, bl);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl, acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh, acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[a], bm, acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[a], bh, acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bm, acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh, acc[a][b], 0, 0, 0);
+            }
+        }
+    }
+    float *out = partial + (size_t)split * n * n;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + wi + 16 * a + 4 * g + v, k = k0 + wk + 16 * b + l16;
+                if (i < n && k < n) out[(size_t)i * n + k] = acc[a][b][v];
+            }
+}
+
 __device__ __forceinline__ double wcoef(const PlanTables &t, int i) {
     // w_i = x_i^T v
     if (t.kind[i] == ROW_DEFLATED) return t.zraw[t.origin[i]];
@@ -251,7 +351,10 @@ static dctplus_status grad_launch(dctplus_plan_s *p, const float *y, const float
     double *rvec = GT + (size_t)n * n;
     double *qvec = rvec + n;
     double *svec = qvec + n;
-    hipLaunchKernelGGL(k_gram, dim3(nt, nt, nsplit), dim3(256), 0, s, gy, y, partial, batch, n, rows_per);
+    if (p->dtype == DCTPLUS_F32_SPLIT)
+        hipLaunchKernelGGL(k_gram_split, dim3(nt, nt, nsplit), dim3(256), 0, s, gy, y, partial, batch, n, rows_per);
+    else
+        hipLaunchKernelGGL(k_gram, dim3(nt, nt, nsplit), dim3(256), 0, s, gy, y, partial, batch, n, rows_per);
     hipLaunchKernelGGL(k_gram_sum, dim3((unsigned)(((size_t)n * n + 255) / 256)), dim3(256), 0, s,
                        (const float *)partial, nsplit, n, G, GT);
     hipLaunchKernelGGL(k_grad_vec, dim3((n + 3) / 4), dim3(256), 0, s, p->t, (const double *)G, (const double *)GT,
