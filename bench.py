@@ -445,12 +445,11 @@ def main():
             torch.cuda.empty_cache()
         # rank-k updates (Cor. 4.5): three added edges (weights in [0.5, 2]) on the workload-2
         # batch; the composite Cauchy factor goes through the same factored kernel
-        import oracle
         g3 = np.random.default_rng(4242)
         rk_rhos, rk_V = [], []
         for _ in range(3):
             i3, j3 = sorted(int(t) for t in g3.choice(n, 2, replace=False))
-            r3, v3 = oracle.candidate_update(n, 1, i3, j3, float(g3.uniform(0.5, 2.0)))
+            r3, v3 = workloads.edge_update(n, i3, j3, float(g3.uniform(0.5, 2.0)))
             rk_rhos.append(r3)
             rk_V.append(v3)
         torch.cuda.synchronize()
@@ -462,7 +461,7 @@ def main():
         pk.close()
         # DTT+ (Sec. 4.3): a rank-one update of the ADST graph, the DST-VII as the base
         # (general-base plan: the dense product with X^T, split-BF16)
-        lam7, U7 = oracle.dst7_basis(n)
+        lam7, U7 = workloads.adst_base(n)
         pd = Plan(n, W["rho"], W["v"], dtype="f32split", base=(lam7, U7))
         td = time_pair(torch, lambda: pd.forward(x, out=y), lambda: pd.adjoint(y, out=xr), args.steps, args.warmup)
         pd.close()

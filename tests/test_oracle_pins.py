@@ -626,6 +626,27 @@ def test_dst7_basis_is_the_adst_graph(n):
     assert np.all(np.diff(lam) > 0)
 
 
+@pytest.mark.parametrize("n", [8, 64])
+def test_benchmark_inputs_are_the_graphs_they_name(n):
+    """The benchmark's rank-k and DTT+ inputs come from the input module: an added edge
+    gives the Laplacian of the edge, and the ADST base diagonalises the path with its unit
+    self-loop at vertex 0 (and equals the oracle's DST-VII)."""
+    for i, j, w in [(0, n - 1, 1.0), (2, n // 2, 0.6)]:
+        rho, v = workloads.edge_update(n, i, j, w)
+        d = np.zeros(n)
+        d[i], d[j] = 1.0, -1.0
+        L_edge = oracle.laplacian(n, 0.0, np.zeros(n)) + w * np.outer(d, d)
+        assert np.abs(oracle.laplacian(n, rho, v) - L_edge).max() < 1e-14
+    lam, U = workloads.adst_base(n)
+    e0 = np.zeros(n)
+    e0[0] = 1.0
+    L = oracle.laplacian(n, 1.0, e0)
+    assert np.abs(U.T @ U - np.eye(n)).max() < 1e-12
+    assert np.abs(L @ U - U * lam[None, :]).max() < 1e-12
+    lam_o, U_o = oracle.dst7_basis(n)
+    assert np.abs(lam - lam_o).max() < 1e-14 and np.abs(U - U_o).max() < 1e-14
+
+
 @pytest.mark.parametrize("n", [8, 32, 64])
 def test_dtt_plus_equals_the_rank_two_path_chain(n):
     """DTT+: a rank-one update of the ADST graph (DST-VII base) is the path graph with

@@ -53,6 +53,23 @@ def edge_vector(n: int, i: int, j: int) -> np.ndarray:
     return v
 
 
+def edge_update(n: int, i: int, j: int, w: float):
+    """(rho, v) of an added edge (i, j) of weight w: w (e_i - e_j)(e_i - e_j)^T = 2w v v^T
+    with the unit v = (e_i - e_j)/sqrt(2)."""
+    return 2.0 * float(w), edge_vector(n, i, j)
+
+
+def adst_base(n: int):
+    """The base graph of the DTT+ workloads as a (lambda, U) input: the path with a unit
+    self-loop at vertex 0 (the ADST graph, Sec. 4.3), whose eigenpairs have the closed
+    form lambda_k = 2 - 2 cos(pi (2k+1)/(2n+1)), U[j, k] = 2/sqrt(2n+1) sin(pi (j+1)(2k+1)/(2n+1))
+    (the DST-VII), ascending in k."""
+    t = np.pi * (2.0 * np.arange(n) + 1.0) / (2 * n + 1)
+    lam = 2.0 - 2.0 * np.cos(t)
+    U = (2.0 / np.sqrt(2 * n + 1)) * np.sin(np.outer(np.arange(1, n + 1), t))
+    return lam, U
+
+
 def workload1(batch: int = 1024, n: int = 64):
     g = rng(1)
     v = np.zeros(n)
