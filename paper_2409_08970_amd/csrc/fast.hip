@@ -63,10 +63,38 @@ __host__ __device__ constexpr int fast_nsig_max(int logn) {
 // scratch from n = 2048 on
 constexpr int kMaxLogLds = 12, kMinLogGlobal = 11;
 
+// LDS stage of the kernels whose per-signal buffer is in global memory, in bytes:
+// 64 KiB, or none where the signal's own rows in LDS leave too little room for a
+// stage that pays (FP64 signals from n = 16384: a 16 KiB stage saved one pass of
+// four and measured slower)
+__host__ __device__ constexpr size_t stage_bytes(int logn, int tdsz) {
+    return ((size_t)tdsz << logn) <= 65536 ? 65536 : 0;
+}
+
+// log2 of the complex elements of type T the stage holds (0: no stage)
+template <typename T>
+__host__ __device__ constexpr int stage_log_elems(size_t stage) {
+    int l = 0;
+    while ((sizeof(cplx<T>) << (l + 1)) <= stage) ++l;
+    return stage ? l : 0;
+}
+
+// the kernels' FFTs: in LDS, or in global memory with the sub-transforms that fit
+// staged through the LDS stage at smem[0] (2^logS elements; logS = 0: no stage)
+template <bool kLds, typename T>
+__device__ __forceinline__ void fast_fft(cplx<T> *buf, int ns, int stride, int logN, const cplx<T> *__restrict__ tw,
+                                         int logT, const RadixPlan &rp, unsigned char *smem, int logS,
+                                         bool zero_mid = false) {
+    if constexpr (kLds)
+        fft_dif(buf, ns, stride, logN, tw, logT, rp, zero_mid);
+    else
+        fft_dif_staged(buf, ns, stride, logN, tw, logT, rp, zero_mid, reinterpret_cast<cplx<T> *>(smem), logS);
+}
+
 struct FastCfg {
     int nsig, threads;
     bool big_in_lds;
-    size_t lds;
+    size_t lds, lds_max;
 };
 
 // double d of a signal's complex FP64 FFT buffer, the place where the real
@@ -100,7 +128,9 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t
         big = reinterpret_cast<double *>(smem);
     else
         big = gscratch + (size_t)blockIdx.x * nsig * BD;
-    size_t off = kLds ? sizeof(double) * (size_t)nsig * BD : 0;
+    constexpr size_t kStage = kLds ? 0 : stage_bytes(LOGN, sizeof(TD));   // LDS stage at smem[0]
+    constexpr int kLogST = stage_log_elems<TD>(kStage), kLogSD = stage_log_elems<double>(kStage);
+    size_t off = kLds ? sizeof(double) * (size_t)nsig * BD : kStage;
     TD *sd = reinterpret_cast<TD *>(smem + off);
     off += sizeof(TD) * (size_t)nsig * n;
     off = (off + 7) & ~size_t(7);
@@ -132,7 +162,7 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t
     }
     __syncthreads();
     constexpr RadixPlan rpA = radix_plan(logn - 1, kPlanSig, nthr);
-    fft_dif(Zf, ns, strideZ, logn - 1, twd, logT, rpA);
+    fast_fft<kLds>(Zf, ns, strideZ, logn - 1, twd, logT, rpA, smem, kLogST);
     // 2. the DCT's outputs X_k, X_{n-k} (thread of k), and with them the four values of
     //    the odd extension u (length 2n) of h = hz * s_d that they give: u(q) at double
     //    n + q of the signal's buffer, i.e. n complex points from double n on (under the
@@ -162,7 +192,7 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t
     }
     __syncthreads();
     constexpr RadixPlan rpB = radix_plan(logn, kPlanSig, nthr);
-    fft_dif(Bc + n / 2, ns, strideB, logn, t.tw64, logT, rpB);
+    fast_fft<kLds>(Bc + n / 2, ns, strideB, logn, t.tw64, logT, rpB, smem, kLogSD);
 
     // 3. c = DST-I(h), times the window deconvolution; written as the odd
     //    extension q (length 4n, zero for n <= l <= 3n) in doubles [0, n) and (3n, 4n)
@@ -194,7 +224,7 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t
     }
 
     // 4. grid G_m = sum_l chat_l sin(pi l m / 2n), m = 0..2n (DST-I of length 2n)
-    fft_dif(Bc, ns, strideB, logn + 1, t.tw64, logT, rpC, kPruned);
+    fast_fft<kLds>(Bc, ns, strideB, logn + 1, t.tw64, logT, rpC, smem, kLogSD, kPruned);
     // pairs (m, 2n - m), m = 1..n, staged in registers (the output overwrites the FFT data)
     double gv[2 * kRounds];
 #pragma unroll
@@ -330,7 +360,9 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_adj(PlanTables t
         big = reinterpret_cast<double *>(smem);
     else
         big = gscratch + (size_t)blockIdx.x * nsig * BD;
-    size_t off = kLds ? sizeof(double) * (size_t)nsig * BD : 0;
+    constexpr size_t kStage = kLds ? 0 : stage_bytes(LOGN, sizeof(TD));   // LDS stage at smem[0]
+    constexpr int kLogST = stage_log_elems<TD>(kStage), kLogSD = stage_log_elems<double>(kStage);
+    size_t off = kLds ? sizeof(double) * (size_t)nsig * BD : kStage;
     TD *yb = reinterpret_cast<TD *>(smem + off);   // input rows in bin order (0 for empty bins)
     off += sizeof(TD) * (size_t)nsig * n;
     off = (off + 7) & ~size_t(7);
@@ -425,7 +457,7 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_adj(PlanTables t
     cplx<double> *Bc = reinterpret_cast<cplx<double> *>(big);
     const int strideB = BD / 2;
     constexpr RadixPlan rpC = radix_plan(logn + 1, kPlanSig, nthr);
-    fft_dif(Bc, ns, strideB, logn + 1, t.tw64, logT, rpC);
+    fast_fft<kLds>(Bc, ns, strideB, logn + 1, t.tw64, logT, rpC, smem, kLogSD);
 
     // r_l = sum_m G'_m sin(pi l m / 2n) for l < n, times the deconvolution;
     // staged in registers, then written as the odd extension (length 2n) for DST-I
@@ -458,7 +490,7 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_adj(PlanTables t
     }
     __syncthreads();
     constexpr RadixPlan rpB = radix_plan(logn, kPlanSig, nthr);
-    fft_dif(Bc, ns, strideB, logn, t.tw64, logT, rpB);
+    fast_fft<kLds>(Bc, ns, strideB, logn, t.tw64, logT, rpB, smem, kLogSD);
 
     // s_d' = hz * DST-I(c') + deflated rows + exact rows + the compensation, in doubles [2n, 3n)
     for (int g = tid; g < ns * n; g += nthr) {
@@ -483,7 +515,7 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_adj(PlanTables t
     }
     __syncthreads();
     constexpr RadixPlan rpA = radix_plan(logn - 1, kPlanSig, nthr);
-    fft_dif(Zf, ns, strideZ, logn - 1, twd, logT, rpA);
+    fast_fft<kLds>(Zf, ns, strideZ, logn - 1, twd, logT, rpA, smem, kLogST);
     for (int g = tid; g < ns * n; g += nthr) {
         const int s = g / n, j = g % n;
         x[(s0 + s) * n + j] = (TIO)dct3_sample(Zf + (size_t)s * strideZ, j, logn, rpA);
@@ -506,11 +538,13 @@ FastCfg fast_config(const dctplus_plan_s *p, int cfg = 0) {
     size_t budget = (size_t)lds_max - 4096;
     if (budget > 150 * 1024) budget = 150 * 1024;
     c.big_in_lds = (per_big + per_small) <= budget;
+    const size_t stage = c.big_in_lds ? 0 : stage_bytes(p->logn, (int)tdsz);
     int ns = fast_nsig_max(p->logn);
-    while (ns > 1 && (size_t)ns * ((c.big_in_lds ? per_big : 0) + per_small) > budget) ns >>= 1;
+    while (ns > 1 && stage + (size_t)ns * ((c.big_in_lds ? per_big : 0) + per_small) > budget) ns >>= 1;
     if (cfg >= 2) ns = ns >> (cfg - 1) > 0 ? ns >> (cfg - 1) : 1;
     c.nsig = ns;
-    c.lds = (size_t)ns * ((c.big_in_lds ? per_big : 0) + per_small) + 64 + 8 * 16;   // + exact-row partials
+    c.lds = stage + (size_t)ns * ((c.big_in_lds ? per_big : 0) + per_small) + 64 + 8 * 16;   // + exact-row partials
+    c.lds_max = (size_t)lds_max;
     return c;
 }
 
@@ -557,6 +591,9 @@ dctplus_status fast_apply(dctplus_plan_s *p, const void *in, void *out, int64_t 
     const int n = (int)p->n;
     if ((size_t)c.nsig * n > (size_t)kMaxPair * c.threads)
         return fail(DCTPLUS_EUNSUPPORTED, "n = %d too large for the FAST route", n);
+    if (c.lds > c.lds_max)
+        return fail(DCTPLUS_EUNSUPPORTED, "FAST route at n = %d needs %zu bytes of LDS (%d exact rows)", n, c.lds,
+                    p->t.ndirect);
     const int64_t blocks = (batch + c.nsig - 1) / c.nsig;
     double *scratch = nullptr;
     if (!c.big_in_lds) {

@@ -143,10 +143,24 @@ __device__ __forceinline__ int fft_slot(int e) {
     return e ^ (h & ((1 << B) - 1));
 }
 
+// Element e of an FFT buffer in global memory: a uniform base plus a 32-bit byte
+// offset, so that an address costs one register (the base stays scalar).  The
+// buffer must be under 4 GiB.
+template <typename T>
+__device__ __forceinline__ cplx<T> buf_ld(const cplx<T> *buf, int e) {
+    return *reinterpret_cast<const cplx<T> *>(reinterpret_cast<const char *>(buf) +
+                                              (uint64_t)((uint32_t)e * (uint32_t)sizeof(cplx<T>)));
+}
+template <typename T>
+__device__ __forceinline__ void buf_st(cplx<T> *buf, int e, cplx<T> a) {
+    *reinterpret_cast<cplx<T> *>(reinterpret_cast<char *>(buf) + (uint64_t)((uint32_t)e * (uint32_t)sizeof(cplx<T>))) = a;
+}
+
 // ZMID: the first pass of a transform whose input is zero on its middle half
 // (points [N/4, 3N/4)); with radix R >= 4 those are the butterfly inputs
 // r in [R/4, 3R/4), which are taken as zero instead of read.
-template <int LR, typename T, bool ZMID = false>
+// STREAM: the buffer is in global memory (buf_ld / buf_st); otherwise in LDS.
+template <int LR, typename T, bool ZMID = false, bool STREAM = false>
 __device__ __forceinline__ void fft_pass(cplx<T> *buf, int nsig, int stride, int logN, int logL,
                                          const cplx<T> *__restrict__ tw, int logNtw, int tid, int nthr) {
     constexpr int R = 1 << LR;
@@ -164,13 +178,16 @@ __device__ __forceinline__ void fft_pass(cplx<T> *buf, int nsig, int stride, int
         const int rem = g & ((1 << lg) - 1);
         const int sub = rem >> logm;
         const int j = rem & (m - 1);
-        cplx<T> *sig = buf + (size_t)s * stride;
         const int a = fft_slot<T>((sub << logL) + j);
+        const int sb = s * stride;
+        cplx<T> *sig = buf + (size_t)s * stride;
         cplx<T> x[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (ZMID && R >= 4 && r >= R / 4 && r < 3 * R / 4)
                 x[r] = cplx<T>{T(0), T(0)};
+            else if constexpr (STREAM)
+                x[r] = buf_ld(buf, sb + (a ^ roff[r]));
             else
                 x[r] = sig[a ^ roff[r]];
         }
@@ -208,7 +225,12 @@ __device__ __forceinline__ void fft_pass(cplx<T> *buf, int nsig, int stride, int
             }
         }
 #pragma unroll
-        for (int r = 0; r < R; ++r) sig[a ^ roff[r]] = x[r];
+        for (int r = 0; r < R; ++r) {
+            if constexpr (STREAM)
+                buf_st(buf, sb + (a ^ roff[r]), x[r]);
+            else
+                sig[a ^ roff[r]] = x[r];
+        }
     }
 }
 
@@ -238,6 +260,83 @@ __device__ __forceinline__ void fft_dif(cplx<T> *buf, int nsig, int stride, int 
             }
         }
         logL -= lr;
+        __syncthreads();
+    }
+}
+
+// The same transform of a buffer in global memory, with an LDS stage of 2^logS
+// complex elements.  The passes run in global memory only while the sub-transforms
+// are longer than the stage; DIF leaves sub-transform q of length L = 2^logL on the
+// contiguous positions [qL, (q+1)L), so from there on the remaining passes run on
+// whole sub-transforms staged through LDS (as many per fill as the stage holds):
+// one read and one write of the buffer instead of one per remaining pass.  The
+// passes and their order are those of rp, so the output is the same as fft_dif's
+// (consumers read it through dif_pos and fft_slot as usual).  A position's slot
+// splits as fft_slot(qL + e) = fft_slot(qL) ^ fft_slot(e) (fft_slot is linear and
+// the two have no bits in common), so a staged sub-transform keeps the bank
+// swizzle of a transform of length L.  zero_mid as for fft_dif (the staged copy
+// of an unwritten middle is never read).
+template <typename T>
+__device__ __forceinline__ void fft_dif_staged(cplx<T> *buf, int nsig, int stride, int logN,
+                                               const cplx<T> *__restrict__ tw, int logNtw, const RadixPlan &rp,
+                                               bool zero_mid, cplx<T> *stage, int logS) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    int logL = logN, i = 0;
+    for (; i < rp.np && logL > logS; ++i) {
+        const int lr = rp.lr(i);
+        if (i == 0 && zero_mid) {
+            switch (lr) {
+                case 2: fft_pass<2, T, true, true>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
+                case 3: fft_pass<3, T, true, true>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
+                default: fft_pass<4, T, true, true>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
+            }
+        } else {
+            switch (lr) {
+                case 1: fft_pass<1, T, false, true>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
+                case 2: fft_pass<2, T, false, true>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
+                case 3: fft_pass<3, T, false, true>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
+                default: fft_pass<4, T, false, true>(buf, nsig, stride, logN, logL, tw, logNtw, tid, nthr); break;
+            }
+        }
+        logL -= lr;
+        __syncthreads();
+    }
+    if (i == rp.np) return;
+    const int logB = logL, lgq = logN - logL;       // sub-transform length, log2 of their count per signal
+    const int per = 1 << (logS - logB), nsub = nsig << lgq;
+    for (int q0 = 0; q0 < nsub; q0 += per) {
+        const int cnt = nsub - q0 < per ? nsub - q0 : per;
+        for (int e = tid; e < (cnt << logB); e += nthr) {
+            const int q = q0 + (e >> logB);
+            stage[e] = buf_ld(buf, (q >> lgq) * stride + (fft_slot<T>((q & ((1 << lgq) - 1)) << logB) ^
+                                                            (e & ((1 << logB) - 1))));
+        }
+        __syncthreads();
+        int l2 = logB;
+        for (int k = i; k < rp.np; ++k) {
+            const int lr = rp.lr(k);
+            if (k == 0 && zero_mid) {
+                switch (lr) {
+                    case 2: fft_pass<2, T, true>(stage, cnt, 1 << logB, logB, l2, tw, logNtw, tid, nthr); break;
+                    case 3: fft_pass<3, T, true>(stage, cnt, 1 << logB, logB, l2, tw, logNtw, tid, nthr); break;
+                    default: fft_pass<4, T, true>(stage, cnt, 1 << logB, logB, l2, tw, logNtw, tid, nthr); break;
+                }
+            } else {
+                switch (lr) {
+                    case 1: fft_pass<1, T>(stage, cnt, 1 << logB, logB, l2, tw, logNtw, tid, nthr); break;
+                    case 2: fft_pass<2, T>(stage, cnt, 1 << logB, logB, l2, tw, logNtw, tid, nthr); break;
+                    case 3: fft_pass<3, T>(stage, cnt, 1 << logB, logB, l2, tw, logNtw, tid, nthr); break;
+                    default: fft_pass<4, T>(stage, cnt, 1 << logB, logB, l2, tw, logNtw, tid, nthr); break;
+                }
+            }
+            l2 -= lr;
+            __syncthreads();
+        }
+        for (int e = tid; e < (cnt << logB); e += nthr) {
+            const int q = q0 + (e >> logB);
+            buf_st(buf, (q >> lgq) * stride + (fft_slot<T>((q & ((1 << lgq) - 1)) << logB) ^ (e & ((1 << logB) - 1))),
+                   stage[e]);
+        }
         __syncthreads();
     }
 }

@@ -248,6 +248,29 @@ def test_fp64_self_loop_dst7(route):
 TOL_FAST64 = 1e-11
 
 
+@pytest.mark.parametrize("n", [8192, 16384])
+def test_fp64_fast_parity_buffer_in_global_memory(n):
+    """FP64 signals on the FAST route where the per-signal buffer lives in global
+    memory and the FFTs are staged through LDS (a 64 KiB stage at n = 8192, 16 KiB at
+    n = 16384): the workload-3 graph (dense v, rho = 0.5) on two signals against the
+    secular semi-oracle, forward and adjoint.  The bar grows with n: the h-scale of
+    Alg. 1 step 4 divides by sin(pi j / n) >= sin(pi / n) ~ pi / n, so the rounding of
+    the FP64 transforms after it, relative to the output, grows in proportion to n;
+    1e-11 holds with a 5x margin up to n = 4096 (below), hence 1e-11 * n / 4096."""
+    W = workloads.workload3(n, "dense", batch=2)
+    rho, v = W["rho"], W["v"]
+    x = W["x"].astype(np.float64)
+    yin = np.random.default_rng(n + 1).standard_normal((2, n))
+    p = make_plan(n, rho, v, "fast", dtype="f64")
+    y = run(p, x)
+    xa = run(p, yin, adjoint=True)
+    p.close()
+    sp = oracle.semi_plan(n, rho, v)
+    tol = TOL_FAST64 * n / 4096
+    assert relerr(y, oracle.semi_forward(n, rho, v, x, sp)) <= tol, n
+    assert relerr(xa, oracle.semi_adjoint(n, rho, v, yin, sp)) <= tol, n
+
+
 @pytest.mark.parametrize("n,batch", [(8, 75), (64, 75), (256, 75), (1024, 20), (4096, 4)])
 @pytest.mark.parametrize("kind", ["dense", "loopn", "edge", "negative"])
 def test_fp64_fast_parity(n, batch, kind):
