@@ -79,6 +79,12 @@ __host__ __device__ constexpr int stage_log_elems(size_t stage) {
     return stage ? l : 0;
 }
 
+// radix plan of a kernel FFT: made for the stage when the buffer is in global memory
+// (logS = 0: no stage)
+__host__ __device__ constexpr RadixPlan fast_plan(bool lds, int logN, int logS, int nsig, int nthreads) {
+    return lds ? radix_plan(logN, nsig, nthreads) : radix_plan_staged(logN, logS, nsig, nthreads);
+}
+
 // the kernels' FFTs: in LDS, or in global memory with the sub-transforms that fit
 // staged through the LDS stage at smem[0] (2^logS elements; logS = 0: no stage)
 template <bool kLds, typename T>
@@ -161,7 +167,7 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t
         }
     }
     __syncthreads();
-    constexpr RadixPlan rpA = radix_plan(logn - 1, kPlanSig, nthr);
+    constexpr RadixPlan rpA = fast_plan(kLds, logn - 1, kLogST, kPlanSig, nthr);
     fast_fft<kLds>(Zf, ns, strideZ, logn - 1, twd, logT, rpA, smem, kLogST);
     // 2. the DCT's outputs X_k, X_{n-k} (thread of k), and with them the four values of
     //    the odd extension u (length 2n) of h = hz * s_d that they give: u(q) at double
@@ -191,7 +197,7 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t
         }
     }
     __syncthreads();
-    constexpr RadixPlan rpB = radix_plan(logn, kPlanSig, nthr);
+    constexpr RadixPlan rpB = fast_plan(kLds, logn, kLogSD, kPlanSig, nthr);
     fast_fft<kLds>(Bc + n / 2, ns, strideB, logn, t.tw64, logT, rpB, smem, kLogSD);
 
     // 3. c = DST-I(h), times the window deconvolution; written as the odd
@@ -200,7 +206,7 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t
     // pass has radix >= 4 that pass leaves those points out, and only double 3n, which
     // shares a complex point with the last c, is written here; otherwise the middle is
     // cleared.
-    constexpr RadixPlan rpC = radix_plan(logn + 1, kPlanSig, nthr);
+    constexpr RadixPlan rpC = fast_plan(kLds, logn + 1, kLogSD, kPlanSig, nthr);
     constexpr bool kPruned = rpC.lr(0) >= 2;
     for (int g = tid; g < ns * n; g += nthr) {
         const int s = g / n, l = g % n;
@@ -456,7 +462,7 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_adj(PlanTables t
     __syncthreads();
     cplx<double> *Bc = reinterpret_cast<cplx<double> *>(big);
     const int strideB = BD / 2;
-    constexpr RadixPlan rpC = radix_plan(logn + 1, kPlanSig, nthr);
+    constexpr RadixPlan rpC = fast_plan(kLds, logn + 1, kLogSD, kPlanSig, nthr);
     fast_fft<kLds>(Bc, ns, strideB, logn + 1, t.tw64, logT, rpC, smem, kLogSD);
 
     // r_l = sum_m G'_m sin(pi l m / 2n) for l < n, times the deconvolution;
@@ -489,7 +495,7 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_adj(PlanTables t
         }
     }
     __syncthreads();
-    constexpr RadixPlan rpB = radix_plan(logn, kPlanSig, nthr);
+    constexpr RadixPlan rpB = fast_plan(kLds, logn, kLogSD, kPlanSig, nthr);
     fast_fft<kLds>(Bc, ns, strideB, logn, t.tw64, logT, rpB, smem, kLogSD);
 
     // s_d' = hz * DST-I(c') + deflated rows + exact rows + the compensation, in doubles [2n, 3n)
@@ -514,7 +520,7 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_adj(PlanTables t
         Zf[(size_t)s * strideZ + fft_slot<TD>(k)] = dct3_pack<TD>(get, k, logn, twd, logT);
     }
     __syncthreads();
-    constexpr RadixPlan rpA = radix_plan(logn - 1, kPlanSig, nthr);
+    constexpr RadixPlan rpA = fast_plan(kLds, logn - 1, kLogST, kPlanSig, nthr);
     fast_fft<kLds>(Zf, ns, strideZ, logn - 1, twd, logT, rpA, smem, kLogST);
     for (int g = tid; g < ns * n; g += nthr) {
         const int s = g / n, j = g % n;

@@ -92,6 +92,9 @@ __device__ __forceinline__ void dft_reg(cplx<T> *x) {
 struct RadixPlan {
     int np;          // number of passes
     uint32_t code;   // 2 bits per pass: log2(radix) - 1
+    // first pass whose sub-transforms are stored in natural order (a staged
+    // transform, fft_dif_staged); passes before it leave their digits reversed
+    int nat = 32;
     __host__ __device__ constexpr int lr(int i) const { return (int)((code >> (2 * i)) & 3u) + 1; }
 };
 
@@ -108,12 +111,37 @@ __host__ __device__ constexpr RadixPlan radix_plan(int logN, int nsig, int nthre
     return rp;
 }
 
-// Position of frequency k in the digit-reversed output (kept in slot
-// fft_slot of that position).
+// Plan of a transform staged through an LDS stage of 2^logS elements (logS > 0):
+// one pass in global memory over the logN - logS bits that do not fit (at most 4),
+// then the stage's passes, whose sub-transforms are stored back in natural order.
+// The output then sits at position (k mod 2^g) 2^(logN-g) + (k >> g), g = logN - logS:
+// a wave reading consecutive frequencies reads 2^g runs of consecutive elements.
+__host__ __device__ constexpr RadixPlan radix_plan_staged(int logN, int logS, int nsig, int nthreads) {
+    if (logS <= 0 || logN - logS > 4) return radix_plan(logN, nsig, nthreads);
+    RadixPlan rp{0, 0u};
+    int rem = logN;
+    if (logN > logS) {
+        rp.code = (uint32_t)(logN - logS - 1);
+        rp.np = 1;
+        rem = logS;
+    }
+    rp.nat = rp.np;
+    const RadixPlan tail = radix_plan(rem, 1, nthreads);
+    for (int i = 0; i < tail.np; ++i) {
+        rp.code |= (uint32_t)(tail.lr(i) - 1) << (2 * rp.np);
+        ++rp.np;
+    }
+    return rp;
+}
+
+// Position of frequency k in the output (kept in slot fft_slot of that position):
+// digit-reversed, except that the digits of the passes from rp.nat on stay in
+// natural order.
 __device__ __forceinline__ int dif_pos(int k, const RadixPlan &rp, int logN) {
     int p = 0, logL = logN;
     uint32_t code = rp.code;
     for (int i = 0; i < rp.np; ++i) {
+        if (i == rp.nat) return p + k;     // the remaining digits, in natural order
         const int lr = (int)(code & 3u) + 1;
         code >>= 2;
         const int k2 = k & ((1 << lr) - 1);
@@ -333,9 +361,22 @@ __device__ __forceinline__ void fft_dif_staged(cplx<T> *buf, int nsig, int strid
             __syncthreads();
         }
         for (int e = tid; e < (cnt << logB); e += nthr) {
-            const int q = q0 + (e >> logB);
-            buf_st(buf, (q >> lgq) * stride + (fft_slot<T>((q & ((1 << lgq) - 1)) << logB) ^ (e & ((1 << logB) - 1))),
-                   stage[e]);
+            const int q = q0 + (e >> logB), el = e & ((1 << logB) - 1);
+            int ls = fft_slot<T>(el);        // stage slot of the element stored at local position el
+            if (rp.nat == i) {
+                // natural order: position el holds local frequency el, which the staged
+                // passes left at the digit-reversed local position
+                int pos = 0, lL = logB, kk = el;
+                for (int k = i; k < rp.np; ++k) {
+                    const int lr = rp.lr(k);
+                    lL -= lr;
+                    pos += (kk & ((1 << lr) - 1)) << lL;
+                    kk >>= lr;
+                }
+                ls = fft_slot<T>(pos);
+            }
+            buf_st(buf, (q >> lgq) * stride + (fft_slot<T>((q & ((1 << lgq) - 1)) << logB) ^ fft_slot<T>(el)),
+                   stage[(e & ~((1 << logB) - 1)) + ls]);
         }
         __syncthreads();
     }
