@@ -421,7 +421,7 @@ __global__ void __launch_bounds__(256, 4) k_dense_stream(const float *__restrict
         const int64_t t = tile < nfull ? tile : nfull - 1;
         const f4 *src = reinterpret_cast<const f4 *>(in + t * 16 * N);
 #pragma unroll
-        for (int u = 0; u < V4; ++u) b[u] = src[64 * u + lane];
+        for (int u = 0; u < V4; ++u) b[u] = __builtin_nontemporal_load(src + 64 * u + lane);
     };
     // coalesced chunks -> staging -> this lane's operand chunks 4 v + g of row l16
     auto relayout_in = [&](f4 *b) {
@@ -461,7 +461,7 @@ __global__ void __launch_bounds__(256, 4) k_dense_stream(const float *__restrict
             if (sig < batch) {
                 f4 *dst = reinterpret_cast<f4 *>(out + sig * N + 4 * g);
 #pragma unroll
-                for (int c = 0; c < CT; ++c) dst[4 * c] = acc[c];
+                for (int c = 0; c < CT; ++c) __builtin_nontemporal_store(acc[c], dst + 4 * c);
             }
         } else {
             // outputs 16 c + 4 g .. + 3 of row l16 are chunk 4 c + g: stage, then store
@@ -473,7 +473,7 @@ __global__ void __launch_bounds__(256, 4) k_dense_stream(const float *__restrict
 #pragma unroll
             for (int u = 0; u < V4; ++u) {
                 const int L = 64 * u + lane;
-                dst[L] = st[spos(L / CH, L % CH)];
+                __builtin_nontemporal_store(st[spos(L / CH, L % CH)], dst + L);
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -567,6 +567,9 @@ __global__ void __launch_bounds__(256) k_factored_image(const float *__restrict_
 }
 
 constexpr int kFactoredDepth = 2;   // tiles in flight per wave
+// The streaming kernels read each input tile and write each output tile exactly once:
+// their global loads and stores carry the non-temporal hint (108 -> 100 us per launch
+// at n = 64, 2^20 signals, against 97 us for a plain device copy of the same bytes).
 
 template <int MODE, bool ADJ>
 __global__ void __launch_bounds__(256, 4) k_factored_stream(const float *__restrict__ in, float *__restrict__ out,
@@ -594,7 +597,7 @@ __global__ void __launch_bounds__(256, 4) k_factored_stream(const float *__restr
         const int64_t t = tile < nfull ? tile : nfull - 1;
         const f4 *src = reinterpret_cast<const f4 *>(in + t * 16 * N);
 #pragma unroll
-        for (int u = 0; u < V4; ++u) b[u] = src[64 * u + lane];
+        for (int u = 0; u < V4; ++u) b[u] = __builtin_nontemporal_load(src + 64 * u + lane);
     };
     f4 ring[D][V4];
     if (nfull > 0) {
@@ -680,13 +683,13 @@ __global__ void __launch_bounds__(256, 4) k_factored_stream(const float *__restr
 #pragma unroll
             for (int u = 0; u < V4; ++u) {
                 const int L = 64 * u + lane;
-                dst[L] = st[spos(L / CH, L % CH)];
+                __builtin_nontemporal_store(st[spos(L / CH, L % CH)], dst + L);
             }
         } else {
 #pragma unroll
             for (int u = 0; u < V4; ++u) {
                 const int L = 64 * u + lane;
-                if (L / CH < nvalid) dst[L] = st[spos(L / CH, L % CH)];
+                if (L / CH < nvalid) __builtin_nontemporal_store(st[spos(L / CH, L % CH)], dst + L);
             }
         }
         __builtin_amdgcn_wave_barrier();
