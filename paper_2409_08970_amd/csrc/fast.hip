@@ -528,8 +528,11 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_adj(PlanTables t
     }
 }
 
-// cfg (the tuner's choice): 0 or 1 = the built-in signals per workgroup, 2 = half, 3 = a quarter
-FastCfg fast_config(const dctplus_plan_s *p, int cfg = 0) {
+// cfg (the tuner's choice): 0 or 1 = the built-in signals per workgroup, 2 = half, 3 = a quarter.
+// The built-in choice takes fewer signals per workgroup while a batch of `batch` signals
+// would leave CUs without a workgroup and the smaller workgroups still run in one round
+// (batch 0: no such adjustment).
+FastCfg fast_config(const dctplus_plan_s *p, int cfg = 0, int64_t batch = 0) {
     const int n = (int)p->n;
     const int nd = p->t.ndirect;
     const size_t tdsz = (p->dtype == DCTPLUS_F64) ? 8 : 4;
@@ -547,7 +550,15 @@ FastCfg fast_config(const dctplus_plan_s *p, int cfg = 0) {
     const size_t stage = c.big_in_lds ? 0 : stage_bytes(p->logn, (int)tdsz);
     int ns = fast_nsig_max(p->logn);
     while (ns > 1 && stage + (size_t)ns * ((c.big_in_lds ? per_big : 0) + per_small) > budget) ns >>= 1;
-    if (cfg >= 2) ns = ns >> (cfg - 1) > 0 ? ns >> (cfg - 1) : 1;
+    if (cfg >= 2) {
+        ns = ns >> (cfg - 1) > 0 ? ns >> (cfg - 1) : 1;
+    } else if (batch > 0) {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || ncu <= 0)
+            ncu = 256;
+        // halve while the halved grid still fits one workgroup per CU (one round)
+        while (ns > 1 && (batch + ns / 2 - 1) / (ns / 2) <= ncu) ns >>= 1;
+    }
     c.nsig = ns;
     c.lds = stage + (size_t)ns * ((c.big_in_lds ? per_big : 0) + per_small) + 64 + 8 * 16;   // + exact-row partials
     c.lds_max = (size_t)lds_max;
@@ -593,7 +604,7 @@ int fast_tune_count(const dctplus_plan_s *p) {
 
 dctplus_status fast_apply(dctplus_plan_s *p, const void *in, void *out, int64_t batch, bool adjoint,
                           hipStream_t s) {
-    const FastCfg c = fast_config(p, tuned(p, adjoint, batch));
+    const FastCfg c = fast_config(p, tuned(p, adjoint, batch), batch);
     const int n = (int)p->n;
     if ((size_t)c.nsig * n > (size_t)kMaxPair * c.threads)
         return fail(DCTPLUS_EUNSUPPORTED, "n = %d too large for the FAST route", n);
