@@ -10,8 +10,8 @@ value = batch * n / (time per step): signal-samples per second through the
 round trip.  Beside it: the dense GFT (the paper's naive product y = X^T x,
 the DCT folded into one matrix) on the same GPU, with our MFMA kernel and
 with torch.matmul, the BF16-operand dense route, the O(n log n) route, the
-large-graph workloads at n = 4096 and 16384 (with the FP64-vector roofline
-of the O(n log n) kernels), the roofline of the dominant kernel (HIP events
+large-graph workloads (256 signals at n = 1024, 4096 and 16384, with the
+FP64-vector roofline of the O(n log n) kernels), the roofline of the dominant kernel (HIP events
 on its launch stream), and the FP64 oracle timed on the host cores (a
 baseline, not a target).
 
@@ -399,7 +399,7 @@ def main():
         comp["n1024_workload"] = mid
         del A, At, x3, y3, r3
         # large graphs: 256 N(0,1) signals, dense unit v, rho = 0.5
-        for nl in (4096, 16384):
+        for nl in (1024, 4096, 16384):
             W3 = workloads.workload3(nl, "dense")
             x3 = torch.from_numpy(W3["x"]).to(dev)
             y3 = torch.empty_like(x3)
@@ -432,15 +432,20 @@ def main():
                                max(20, args.steps), 2)
                 large["dense_f32split"] = {"ms_per_step": t3[0], "value": 256 * nl / (t3[0] * 1e-3)}
                 ps.close()
+            # AUTO as a user gets it (at n = 1024 it runs batches below 1,024 signals on the
+            # FAST route and reports the dense route it keeps for larger ones)
             pa = Plan(nl, W3["rho"], W3["v"], route="auto")
-            large["dct_plus_auto"] = {"route": pa.route, **large[pa.route]}
+            t3 = time_pair(torch, lambda: pa.forward(x3, out=y3), lambda: pa.adjoint(y3, out=r3),
+                           max(20, args.steps), 2)
+            large["dct_plus_auto"] = {"plan_route": pa.route, "ms_per_step": t3[0],
+                                      "value": 256 * nl / (t3[0] * 1e-3)}
             pa.close()
             A = torch.randn(nl, nl, device=dev)
             At = A.t().contiguous()
             t3 = time_pair(torch, lambda: torch.matmul(x3, A, out=y3), lambda: torch.matmul(y3, At, out=r3),
                            max(3, args.steps // 4), 2)[0]
             large["gft_torch_matmul"] = {"ms_per_step": t3, "value": 256 * nl / (t3 * 1e-3)}
-            comp[f"n{nl}_workload"] = large
+            comp["n1024_256_signals" if nl == 1024 else f"n{nl}_workload"] = large
             del A, At, x3, y3, r3
             torch.cuda.empty_cache()
         # rank-k updates (Cor. 4.5): three added edges (weights in [0.5, 2]) on the workload-2

@@ -83,7 +83,9 @@ typedef enum {
 /* How the product with diag(a) C(mu, lambda) diag(z) is formed. */
 typedef enum {
     DCTPLUS_ROUTE_AUTO = 0,  /* FP32: the faster route measured on MI355X, DENSE for n <= 1024,
-                                FAST for n >= 2048; other dtypes: DENSE */
+                                FAST for n >= 2048, and at n = 1024 (one update) FAST for calls
+                                of fewer than 1,024 signals (chosen per call; plan_info reports
+                                DENSE); other dtypes: DENSE */
     DCTPLUS_ROUTE_FAST = 1,  /* Alg. 1 / Thm 3.3: DCT-II, DST-I, sine NUFFT, O(n log n) */
     DCTPLUS_ROUTE_DENSE = 2, /* Thm 3.1: DCT-II, then an MFMA product with the n x n Cauchy factor */
     DCTPLUS_ROUTE_GFT = 3    /* dense GFT (the paper's naive product): MFMA product with X^T */

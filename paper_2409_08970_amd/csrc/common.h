@@ -81,6 +81,7 @@ struct dctplus_plan_s {
     int factored;             // DENSE route keeps the DCT and the Cauchy factor apart
     int defer_dense;          // plan_build leaves the dense operands to the caller (rank-k plans)
     int rank;                 // number of rank-one updates (1 for dctplus_plan)
+    int64_t auto_fast_below = 0;   // AUTO plans on the dense product: batches below this run FAST
     // launch configuration chosen by dctplus_tune, per direction (0 forward, 1 adjoint)
     // and batch bucket floor(log2 batch); 0 = the built-in choice
     int8_t tune_cfg[2][64];
@@ -145,6 +146,11 @@ inline int batch_bucket(int64_t batch) {
     int b = 0;
     while (b < 63 && (int64_t(2) << b) <= batch) ++b;
     return b;
+}
+// the route a call of `batch` signals takes: the plan's, except that an AUTO plan kept on
+// the dense product runs small batches on the FAST route (its tables are always built)
+inline bool use_fast(const dctplus_plan_s *p, int64_t batch) {
+    return p->route == DCTPLUS_ROUTE_FAST || batch < p->auto_fast_below;
 }
 inline int tuned(const dctplus_plan_s *p, bool adjoint, int64_t batch) {
     return p->tune_cfg[adjoint ? 1 : 0][batch_bucket(batch)];

@@ -376,7 +376,7 @@ dctplus_status grad_apply(dctplus_plan_s *p, const float *y, const float *gy, in
     dctplus_status st = grad_check(p, grho, gv);
     if (st != DCTPLUS_OK) return st;
     if (gx) {
-        st = (p->route == DCTPLUS_ROUTE_FAST) ? fast_apply(p, gy, gx, batch, true, s)
+        st = use_fast(p, batch) ? fast_apply(p, gy, gx, batch, true, s)
                                               : dense_apply(p, gy, gx, batch, true, s);
         if (st != DCTPLUS_OK) return st;
     }
@@ -405,7 +405,7 @@ dctplus_status grad_apply_static(dctplus_plan_s *p, const float *y, const float 
         return fail(DCTPLUS_EUNSUPPORTED, "dl/dx on this plan's route needs the plan workspace or a library "
                                           "GEMM; use dctplus_grad");
     if (gx) {
-        st = (p->route == DCTPLUS_ROUTE_FAST) ? fast_apply(p, gy, gx, batch, true, s)
+        st = use_fast(p, batch) ? fast_apply(p, gy, gx, batch, true, s)
                                               : dense_apply(p, gy, gx, batch, true, s);
         if (st != DCTPLUS_OK) return st;
     }

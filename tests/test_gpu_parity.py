@@ -207,6 +207,28 @@ def test_double_eigenvalues_from_mirror_edge(route, n):
     p.close()
 
 
+def test_auto_route_small_batches_at_1024():
+    """AUTO at n = 1024 keeps the dense product for large batches and runs calls of fewer
+    than 1,024 signals on the FAST route (measured faster there): bit-identical to an
+    explicit FAST plan below the switch and to a DENSE plan at and above it, and within
+    the FP32 bar of the semi-oracle on both sides."""
+    n = 1024
+    rho, v = case(n, "dense")
+    sp = oracle.semi_plan(n, rho, v)
+    g = np.random.default_rng(77)
+    pa, pf, pd = make_plan(n, rho, v, "auto"), make_plan(n, rho, v, "fast"), make_plan(n, rho, v, "dense")
+    assert pa.route == "dense"
+    for batch, twin in [(1, pf), (300, pf), (1023, pf), (1024, pd), (1500, pd)]:
+        x = g.standard_normal((batch, n)).astype(np.float32)
+        ya = run(pa, x)
+        assert np.array_equal(ya, run(twin, x)), batch
+        xa = run(pa, x, adjoint=True)
+        assert np.array_equal(xa, run(twin, x, adjoint=True)), batch
+        rows = [0, batch // 2, batch - 1]
+        assert relerr(ya[rows], oracle.semi_forward(n, rho, v, x[rows].astype(np.float64), sp)) <= TOL32
+    pa.close(); pf.close(); pd.close()
+
+
 @pytest.mark.parametrize("n,dtype,expect", [(64, "f32", "dense"), (1024, "f32", "dense"), (2048, "f32", "fast"),
                                             (4096, "f32", "fast"), (16384, "f32", "fast"), (4096, "f64", "dense"),
                                             (16384, "bf16", None), (64, "f64", "dense")])
