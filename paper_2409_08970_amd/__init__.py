@@ -47,7 +47,9 @@ class Plan:
     """Owns one dctplus plan (device tables built on the GPU in FP64).
 
     rho, v: one rank-one update (a float and n values), or k updates for a rank-k plan
-    (k floats and a k x n array, row j = v_j; Cor. 4.5)."""
+    (k floats and a k x n array, row j = v_j; Cor. 4.5).  `route` is the route the plan
+    was built for; an AUTO plan at n = 1024 (FP32) reports "dense" and still runs calls
+    of fewer than 1,024 signals on the FAST route."""
 
     def __init__(self, n: int, rho, v, route: str = "auto", dtype: str = "f32",
                  nufft_width: int = 0, direct_kappa: float = 0.0, defl_tol: float = 0.0, device: int = -1,
