@@ -10,8 +10,9 @@ value = batch * n / (time per step): signal-samples per second through the
 round trip.  Beside it: the dense GFT (the paper's naive product y = X^T x,
 the DCT folded into one matrix) on the same GPU, with our MFMA kernel and
 with torch.matmul, the BF16-operand dense route, the O(n log n) route, the
-large-graph workloads (256 signals at n = 1024, 4096 and 16384, with the
-FP64-vector roofline of the O(n log n) kernels), the roofline of the dominant kernel (HIP events
+large-graph workloads (256 signals at n = 1024, 4096 and 16384, a dense v
+and an added edge, with the FP64-vector roofline of the O(n log n) kernels),
+the FP64 self-loop workload at n = 64, the roofline of the dominant kernel (HIP events
 on its launch stream), and the FP64 oracle timed on the host cores (a
 baseline, not a target).
 
@@ -377,6 +378,22 @@ def main():
             p32.close()
         comp["n32_workload"] = n32
         del x32, y32, r32
+        # workload 1: FP64 signals, n = 64, unit self-loop at vertex 0 (the DST-VII), 1,024
+        # N(0,1) signals; latency-bound (0.5 MiB each way), so time only, per route
+        W1 = workloads.workload1()
+        x1 = torch.from_numpy(W1["x"]).to(dev)
+        y1 = torch.empty_like(x1)
+        r1 = torch.empty_like(x1)
+        fp64 = {"workload": "n=64, rho=1, v=e_0 (DST-VII), 1024 N(0,1) signals, FP64"}
+        for rt in ("auto", "fast"):
+            p1 = Plan(64, W1["rho"], W1["v"], route=rt, dtype="f64")
+            t1 = time_pair(torch, lambda: p1.forward(x1, out=y1), lambda: p1.adjoint(y1, out=r1),
+                           max(20, args.steps), 2)
+            fp64[p1.route if rt == "auto" else "fast_route"] = {"ms_per_step": t1[0],
+                                                                "median_launch_ms": 0.5 * (t1[3] + t1[4])}
+            p1.close()
+        comp["fp64_self_loop_n64"] = fp64
+        del x1, y1, r1
         # a mid-size graph: n = 1024, 8,192 N(0,1) signals (the O(n log n) route against the
         # dense products in FP32 and split-BF16 arithmetic)
         W3 = workloads.workload3(1024, "dense", batch=8192)
@@ -445,6 +462,20 @@ def main():
             t3 = time_pair(torch, lambda: torch.matmul(x3, A, out=y3), lambda: torch.matmul(y3, At, out=r3),
                            max(3, args.steps // 4), 2)[0]
             large["gft_torch_matmul"] = {"ms_per_step": t3, "value": 256 * nl / (t3 * 1e-3)}
+            # the same workload's second graph: one added edge of weight 1 (rho = 2,
+            # v = (e_i - e_j)/sqrt(2)), through AUTO and the FAST route
+            W3e = workloads.workload3(nl, "edge")
+            xe = torch.from_numpy(W3e["x"]).to(dev)
+            edge = {"rho": W3e["rho"], "edge": [int(t) for t in np.flatnonzero(W3e["v"])]}
+            for rt in ("auto", "fast"):
+                pe = Plan(nl, W3e["rho"], W3e["v"], route=rt)
+                te = time_pair(torch, lambda: pe.forward(xe, out=y3), lambda: pe.adjoint(y3, out=r3),
+                               max(20, args.steps), 2)
+                edge["dct_plus_auto" if rt == "auto" else rt] = {"ms_per_step": te[0],
+                                                                 "value": 256 * nl / (te[0] * 1e-3)}
+                pe.close()
+            large["added_edge"] = edge
+            del xe
             comp["n1024_256_signals" if nl == 1024 else f"n{nl}_workload"] = large
             del A, At, x3, y3, r3
             torch.cuda.empty_cache()
