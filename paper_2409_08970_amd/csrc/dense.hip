@@ -1176,13 +1176,14 @@ __global__ void k_split_image(const float *__restrict__ P, int n, uint16_t *__re
 }
 
 int num_cus() {
-    static int ncu = 0;
-    if (ncu == 0) {
+    // initialised once, thread-safely (a local static), from the device current at the first call
+    static const int ncu = [] {
         int dev = 0, v = 0;
-        hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
-        else ncu = 256;
-    }
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            return v;
+        return 256;
+    }();
     return ncu;
 }
 
@@ -1193,32 +1194,34 @@ int persistent_blocks(int64_t nchunks) {
 
 // Grid of the streaming kernels: persistent workgroups, at most the resident capacity (or
 // `wpc` per CU when the tuner chose it), never more than one per four tiles.
+// resident 256-thread workgroups of `kernel` per CU (2 when the runtime cannot tell)
 template <typename K>
-int persistent_grid(K kernel, int &cap_cache, int &per_cache, int64_t ntiles, int wpc) {
-    if (cap_cache == 0) {
-        int per = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess || per <= 0) {
-            (void)hipGetLastError();
-            per = 2;
-        }
-        per_cache = per;
-        cap_cache = per * num_cus();
+int resident_per_cu(K kernel) {
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess || per <= 0) {
+        (void)hipGetLastError();
+        per = 2;
     }
-    const int64_t cap = (wpc > 0 && wpc < per_cache) ? (int64_t)wpc * num_cus() : cap_cache;
+    return per;
+}
+
+int persistent_grid(int per, int64_t ntiles, int wpc) {
+    const int64_t cap = (int64_t)((wpc > 0 && wpc < per) ? wpc : per) * num_cus();
     const int64_t want = (ntiles + 3) / 4;
     return (int)(want < cap ? want : cap);
 }
 
+// (each kernel's occupancy is queried once, in a thread-safe local static)
 template <int N, int MODE>
 int stream_blocks(int64_t ntiles, int wpc) {
-    static int cap = 0, per = 0;
-    return persistent_grid(k_dense_stream<N, MODE>, cap, per, ntiles, wpc);
+    static const int per = resident_per_cu(k_dense_stream<N, MODE>);
+    return persistent_grid(per, ntiles, wpc);
 }
 
 template <int MODE, bool ADJ>
 int factored_blocks(int64_t ntiles, int wpc) {
-    static int cap = 0, per = 0;
-    return persistent_grid(k_factored_stream<MODE, ADJ>, cap, per, ntiles, wpc);
+    static const int per = resident_per_cu(k_factored_stream<MODE, ADJ>);
+    return persistent_grid(per, ntiles, wpc);
 }
 
 // The FP32 dense product for n > 64: 128 x 128 tiles from n = 512 on when they give
