@@ -95,8 +95,17 @@ struct RadixPlan {
     // first pass whose sub-transforms are stored in natural order (a staged
     // transform, fft_dif_staged); passes before it leave their digits reversed
     int nat = 32;
+    // the last pass (radix 2) is left to the readers (fft_out): it only adds and subtracts
+    // neighbouring positions, which a reader can do while reading them
+    bool defer2 = false;
     __host__ __device__ constexpr int lr(int i) const { return (int)((code >> (2 * i)) & 3u) + 1; }
 };
+
+// the plan with its last pass left to the readers when that pass has radix 2
+__host__ __device__ constexpr RadixPlan radix_plan_defer2(RadixPlan rp) {
+    if (rp.np > 1 && rp.lr(rp.np - 1) == 1 && rp.nat >= rp.np) rp.defer2 = true;
+    return rp;
+}
 
 __host__ __device__ constexpr RadixPlan radix_plan(int logN, int nsig, int nthreads) {
     RadixPlan rp{0, 0u};
@@ -150,6 +159,20 @@ __device__ __forceinline__ int dif_pos(int k, const RadixPlan &rp, int logN) {
         p += k2 << logL;
     }
     return p;
+}
+
+template <typename T>
+__device__ __forceinline__ int fft_slot(int e);
+
+// Frequency k of a transform's output (positions from dif_pos, kept in slots fft_slot),
+// with the last radix-2 butterfly applied here when the plan defers it: the pair at
+// positions 2m, 2m + 1 holds (a, b) and the frequencies there are a + b and a - b.
+template <typename T>
+__device__ __forceinline__ cplx<T> fft_out(const cplx<T> *Z, int k, const RadixPlan &rp, int logN) {
+    const int q = dif_pos(k, rp, logN);
+    if (!rp.defer2) return Z[fft_slot<T>(q)];
+    const cplx<T> a = Z[fft_slot<T>(q & ~1)], b = Z[fft_slot<T>(q | 1)];
+    return (q & 1) ? csub(a, b) : cadd(a, b);
 }
 
 // Bank swizzle of the FFT buffers.  Element e of a signal's buffer is kept in
@@ -271,7 +294,8 @@ __device__ __forceinline__ void fft_dif(cplx<T> *buf, int nsig, int stride, int 
                         int logNtw, const RadixPlan &rp, bool zero_mid = false) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     int logL = logN;
-    for (int i = 0; i < rp.np; ++i) {
+    const int np = rp.defer2 ? rp.np - 1 : rp.np;
+    for (int i = 0; i < np; ++i) {
         const int lr = rp.lr(i);
         if (i == 0 && zero_mid) {
             switch (lr) {
@@ -466,8 +490,8 @@ template <typename T>
 __device__ __forceinline__ T dst1_post(const cplx<T> *Zh, int l, int logNn, const RadixPlan &rp,
                                        const cplx<T> *__restrict__ tw, int logNtw) {
     const int Nn = 1 << logNn;
-    const cplx<T> a = Zh[fft_slot<T>(dif_pos(l, rp, logNn))];
-    const cplx<T> b = cconj(Zh[fft_slot<T>(dif_pos(Nn - l, rp, logNn))]);
+    const cplx<T> a = fft_out(Zh, l, rp, logNn);
+    const cplx<T> b = cconj(fft_out(Zh, Nn - l, rp, logNn));
     const cplx<T> E = cscale(cadd(a, b), T(0.5));
     const cplx<T> O = cdiv2i(csub(a, b));
     const cplx<T> w = tw[l << (logNtw - logNn - 1)];   // exp(-2 pi i l / 2Nn)
