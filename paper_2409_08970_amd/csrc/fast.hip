@@ -80,12 +80,9 @@ __host__ __device__ constexpr int stage_log_elems(size_t stage) {
 }
 
 // radix plan of a kernel FFT: made for the stage when the buffer is in global memory
-// (logS = 0: no stage)
+// (logS = 0: no stage); in LDS a last pass of radix 2 is left to the FFT's reader
+// (dct2_post, dst1_post, dct3_sample, through fft_out)
 __host__ __device__ constexpr RadixPlan fast_plan(bool lds, int logN, int logS, int nsig, int nthreads) {
-    return lds ? radix_plan(logN, nsig, nthreads) : radix_plan_staged(logN, logS, nsig, nthreads);
-}
-// the grid DST's plan: in LDS its last pass, when radix 2, is left to its reader (dst1_post)
-__host__ __device__ constexpr RadixPlan grid_plan(bool lds, int logN, int logS, int nsig, int nthreads) {
     return lds ? radix_plan_defer2(radix_plan(logN, nsig, nthreads)) : radix_plan_staged(logN, logS, nsig, nthreads);
 }
 
@@ -210,7 +207,7 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t
     // pass has radix >= 4 that pass leaves those points out, and only double 3n, which
     // shares a complex point with the last c, is written here; otherwise the middle is
     // cleared.
-    constexpr RadixPlan rpC = grid_plan(kLds, logn + 1, kLogSD, kPlanSig, nthr);
+    constexpr RadixPlan rpC = fast_plan(kLds, logn + 1, kLogSD, kPlanSig, nthr);
     constexpr bool kPruned = rpC.lr(0) >= 2;
     for (int g = tid; g < ns * n; g += nthr) {
         const int s = g / n, l = g % n;
@@ -466,7 +463,7 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_adj(PlanTables t
     __syncthreads();
     cplx<double> *Bc = reinterpret_cast<cplx<double> *>(big);
     const int strideB = BD / 2;
-    constexpr RadixPlan rpC = grid_plan(kLds, logn + 1, kLogSD, kPlanSig, nthr);
+    constexpr RadixPlan rpC = fast_plan(kLds, logn + 1, kLogSD, kPlanSig, nthr);
     fast_fft<kLds>(Bc, ns, strideB, logn + 1, t.tw64, logT, rpC, smem, kLogSD);
 
     // r_l = sum_m G'_m sin(pi l m / 2n) for l < n, times the deconvolution;

@@ -435,8 +435,8 @@ template <typename T>
 __device__ __forceinline__ void dct2_post(const cplx<T> *Zh, int k, int logN, const RadixPlan &rp,
                                           const cplx<T> *__restrict__ tw, int logNtw, T &Xk, T &XNk) {
     const int N = 1 << logN, M = N >> 1, logM = logN - 1;
-    const cplx<T> a = Zh[fft_slot<T>(dif_pos(k & (M - 1), rp, logM))];
-    const cplx<T> b = cconj(Zh[fft_slot<T>(dif_pos((M - k) & (M - 1), rp, logM))]);
+    const cplx<T> a = fft_out(Zh, k & (M - 1), rp, logM);
+    const cplx<T> b = cconj(fft_out(Zh, (M - k) & (M - 1), rp, logM));
     const cplx<T> E = cscale(cadd(a, b), T(0.5));
     const cplx<T> O = cdiv2i(csub(a, b));
     const cplx<T> wN = tw[(k << (logNtw - logN)) & ((1 << logNtw) - 1)];
@@ -478,7 +478,7 @@ template <typename T>
 __device__ __forceinline__ T dct3_sample(const cplx<T> *Zf, int j, int logN, const RadixPlan &rp) {
     const int N = 1 << logN, M = N >> 1, logM = logN - 1;
     const int q = (j & 1) ? (N - 1 - (j >> 1)) : (j >> 1);
-    const cplx<T> z = Zf[fft_slot<T>(dif_pos(q >> 1, rp, logM))];
+    const cplx<T> z = fft_out(Zf, q >> 1, rp, logM);
     // conj(z) / M: real part for even q, imaginary part (of the conjugate) for odd q
     return (q & 1) ? (-z.im / T(M)) : (z.re / T(M));
 }
