@@ -908,3 +908,44 @@ def test_autograd_function():
     scale = max(abs(drho), np.abs(dv).max())
     assert abs(rho.grad.item() - drho) <= TOLGRAD * scale
     assert np.abs(v.grad.numpy() - dv).max() <= TOLGRAD * scale
+
+
+def _random_plan_case(g, n_max):
+    n = int(2 ** g.integers(2, int(np.log2(n_max)) + 1))
+    kind = g.choice(["dense", "negative", "loop0", "loopn", "edge"])
+    if kind == "dense":
+        rho, v = float(g.uniform(0.05, 3.0)), workloads.unit_vector(g, n)
+    elif kind == "negative":
+        rho, v = float(-g.uniform(0.05, 1.5)), workloads.unit_vector(g, n)
+    elif kind in ("loop0", "loopn"):
+        v = np.zeros(n)
+        v[0 if kind == "loop0" else -1] = 1.0
+        rho = float(g.uniform(0.1, 2.0))
+    else:
+        i, j = sorted(int(t) for t in g.choice(n, 2, replace=False))
+        rho, v = 2.0 * float(g.uniform(0.2, 2.0)), workloads.edge_vector(n, i, j)
+    return n, kind, rho, v
+
+
+@pytest.mark.parametrize("route", ["fast", "dense", "gft", "auto"])
+def test_random_plans_against_the_semi_oracle(route):
+    """Seeded random plans beyond the fixed cases: n = 4 ... 2048, dense v with
+    rho of either sign, self-loops at either end and added edges of random weight,
+    1 to 8 signals; FP32 signals (and FP64 on the FAST route) against the secular
+    semi-oracle, forward and adjoint, at the FP32 bar and the FP64 FAST bar."""
+    g = np.random.default_rng({"fast": 11, "dense": 12, "gft": 13, "auto": 14}[route])
+    for _ in range(40):
+        n, kind, rho, v = _random_plan_case(g, 2048)
+        dt = "f64" if (route == "fast" and g.random() < 0.3) else "f32"
+        batch = int(g.integers(1, 9))
+        x = g.standard_normal((batch, n))
+        if dt == "f32":
+            x = x.astype(np.float32)
+        p = make_plan(n, rho, v, route, dtype=dt)
+        y, xa = run(p, x), run(p, x, adjoint=True)
+        p.close()
+        sp = oracle.semi_plan(n, rho, v)
+        xd = x.astype(np.float64)
+        bar = TOL32 if dt == "f32" else TOL_FAST64
+        assert relerr(y, oracle.semi_forward(n, rho, v, xd, sp)) <= bar, (n, kind, rho, dt)
+        assert relerr(xa, oracle.semi_adjoint(n, rho, v, xd, sp)) <= bar, (n, kind, rho, dt)
