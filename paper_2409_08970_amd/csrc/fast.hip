@@ -23,7 +23,9 @@
 //
 // The DCT runs in the signal's precision (FP32 for FP32 plans); everything
 // from h onwards runs in FP64.  All per-signal work stays in LDS for
-// n <= 4096 (FP32); larger transforms keep the FP64 buffer in global scratch.
+// n <= 4096 (FP32); larger transforms keep the FP64 buffer in global scratch
+// and run each FFT as one pass in global memory followed by LDS-sized
+// sub-transforms staged through a 64 KiB LDS stage (fft_dif_staged).
 // The placement is a template parameter, so every access to the buffer is an
 // LDS instruction or a global one and no address is ever generic: a generic
 // address formed below the start of the LDS window (a negative index folded

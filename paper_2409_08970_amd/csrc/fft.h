@@ -5,12 +5,15 @@
 // passes (r <= 4).  Each pass gives every thread whole R-point butterflies
 // held in registers; passes are separated by workgroup barriers.  The output
 // is left in digit-reversed order; dif_pos() maps a frequency index to its
-// position, and the consumers of an FFT read through it instead of paying for
-// a reordering pass.  Positions are stored bank-swizzled (fft_slot): the
-// input is written, and the output read, through fft_slot.  Several independent signals (nsig, `stride` complex
-// elements apart) are transformed by one call.  The buffer may live in LDS or
-// in global scratch; callers pass pointers whose address space the compiler
-// can see through the inlining (LDS or global), never a generic one.
+// position, and the consumers of an FFT read through it (fft_out) instead of
+// paying for a reordering pass; a last pass of radix 2 may be left to them as
+// well.  Positions are stored bank-swizzled (fft_slot): the input is written,
+// and the output read, through fft_slot.  Several independent signals (nsig,
+// `stride` complex elements apart) are transformed by one call.  The buffer
+// may live in LDS or in global scratch (fft_dif_staged: one pass in global
+// memory, then LDS-sized sub-transforms staged through LDS and stored back in
+// natural order); callers pass pointers whose address space the compiler can
+// see through the inlining (LDS or global), never a generic one.
 #pragma once
 
 #include "common.h"
