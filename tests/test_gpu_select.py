@@ -244,3 +244,31 @@ def test_select_tune_picks_a_grid_and_keeps_results():
     for a, b in zip(ref, out):
         assert torch.equal(a, b)
     sel.close()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_select_random_shapes(seed):
+    """Seeded random selection problems beyond the fixed workloads: 8 to 24 blocks of
+    random sizes, 1 to 64 signals per block, 1 to 16 candidates of either kind at random
+    vertices (self-loops anywhere, edges between any two vertices) with random positive
+    weights, random c_p and pruning thresholds; every block against the oracle (costs,
+    winners up to ties, the winner's coefficients)."""
+    g = np.random.default_rng(100 + seed)
+    nb = int(g.integers(8, 25))
+    sizes = [int(t) for t in g.choice([4, 8, 16, 32, 64], nb)]
+    S = int(g.integers(1, 65))
+    K = int(g.integers(1, 17))
+    cand = np.zeros((nb, K, 4))
+    for b, n in enumerate(sizes):
+        for r in range(K):
+            if g.random() < 0.4:
+                i = int(g.integers(0, n))
+                cand[b, r] = (0, i, i, g.uniform(0.1, 2.5))
+            else:
+                i, j = (int(t) for t in g.choice(n, 2, replace=False))
+                cand[b, r] = (1, i, j, g.uniform(0.1, 2.5))
+    x = np.concatenate([workloads.ar1(g, S, n, 0.9).reshape(-1) for n in sizes])
+    c_p = int(g.choice([0, 0, 2, 3, 7, 100]))
+    tau = float(g.choice([-1.0, 0.05, 0.1, 0.5, 10.0]))
+    best, cost, y = _run(sizes, cand, S, x, c_p=c_p, tau=tau)
+    _check_blocks(sizes, cand, S, x, best, cost, y, c_p, tau)
