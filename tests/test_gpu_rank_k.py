@@ -183,3 +183,49 @@ def test_rank_k_errors():
     torch.cuda.synchronize()
     assert torch.equal(gx, p.adjoint(gy))
     p.close()
+
+
+def _random_chain(g, n):
+    """k = 2..4 updates, each a dense v with rho of either sign, an added edge or a
+    self-loop at any vertex; the spectrum is simple at every stage."""
+    for _ in range(50):
+        k = int(g.integers(2, 5))
+        rhos, V = [], []
+        for _ in range(k):
+            u = g.random()
+            if u < 0.4:
+                rhos.append(float(g.choice([-1.0, 1.0]) * g.uniform(0.05, 1.5)))
+                V.append(workloads.unit_vector(g, n))
+            elif u < 0.75:
+                i, j = sorted(int(t) for t in g.choice(n, 2, replace=False))
+                rho, v = oracle.candidate_update(n, 1, i, j, float(g.uniform(0.3, 2.0)))
+                rhos.append(rho)
+                V.append(v)
+            else:
+                i = int(g.integers(0, n))
+                rho, v = oracle.candidate_update(n, 0, i, i, float(g.uniform(0.3, 2.0)))
+                rhos.append(rho)
+                V.append(v)
+        if all(np.diff(np.linalg.eigvalsh(oracle.laplacian_rank_k(n, rhos[:j + 1], V[:j + 1]))).min() > 1e-7
+               for j in range(k)):
+            return rhos, np.array(V)
+    raise AssertionError("no chain with simple spectra")
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_rank_k_random_chains(seed):
+    """Seeded random chains of two to four updates (either sign, edges and self-loops
+    anywhere) at n = 8 ... 128 on the dense, factored and GFT routes against the
+    Jacobi oracle of the assembled Laplacian, forward and adjoint."""
+    _torch()
+    g = np.random.default_rng(5000 + seed)
+    n = int(2 ** g.integers(3, 8))
+    rhos, V = _random_chain(g, n)
+    mu, X = oracle.basis_rank_k(n, rhos, V)
+    x = g.standard_normal((37, n)).astype(np.float32)
+    for route in ("dense", "dense-factored", "gft"):
+        p = make(n, rhos, V, route)
+        assert np.abs(p.info["mu"] - mu).max() <= 1e-12 * max(1.0, np.abs(mu).max()), (n, route)
+        assert relerr(run(p, x), oracle.forward(X, x.astype(np.float64))) <= TOL32, (n, route, rhos)
+        assert relerr(run(p, x, adjoint=True), oracle.adjoint(X, x.astype(np.float64))) <= TOL32, (n, route)
+        p.close()
