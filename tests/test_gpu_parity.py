@@ -949,3 +949,30 @@ def test_random_plans_against_the_semi_oracle(route):
         bar = TOL32 if dt == "f32" else TOL_FAST64
         assert relerr(y, oracle.semi_forward(n, rho, v, xd, sp)) <= bar, (n, kind, rho, dt)
         assert relerr(xa, oracle.semi_adjoint(n, rho, v, xd, sp)) <= bar, (n, kind, rho, dt)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_gradient_random_cases(seed):
+    """Seeded random gradient problems: n = 16 ... 256, a dense v with rho of either sign,
+    a self-loop or an added edge anywhere (simple spectrum, so that the basis is
+    differentiable), 64 to 1024 signals, any route; dl/dx, dl/drho and dl/dv against the
+    oracle's perturbation formula at the gradient bars."""
+    g = np.random.default_rng(7000 + seed)
+    for _ in range(50):
+        n = int(2 ** g.integers(4, 9))
+        u = g.random()
+        if u < 0.5:
+            rho, v = float(g.choice([-1.0, 1.0]) * g.uniform(0.1, 1.5)), workloads.unit_vector(g, n)
+        elif u < 0.75:
+            i = int(g.integers(0, n))
+            rho, v = oracle.candidate_update(n, 0, i, i, float(g.uniform(0.3, 2.0)))
+        else:
+            i, j = sorted(int(t) for t in g.choice(n, 2, replace=False))
+            rho, v = oracle.candidate_update(n, 1, i, j, float(g.uniform(0.3, 2.0)))
+        if np.diff(np.linalg.eigvalsh(oracle.laplacian(n, rho, v))).min() > 1e-6:
+            break
+    route = str(g.choice(["fast", "dense", "gft", "auto"]))
+    batch = int(g.integers(64, 1025))
+    x = g.standard_normal((batch, n)).astype(np.float32)
+    gpu, ref = _grad_case(n, rho, v, x, route)
+    _check_grad(gpu, ref)
