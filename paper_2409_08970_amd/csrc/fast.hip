@@ -93,12 +93,17 @@ __host__ __device__ constexpr RadixPlan fast_plan(bool lds, int logN, int logS, 
 template <bool kLds, typename T>
 __device__ __forceinline__ void fast_fft(cplx<T> *buf, int ns, int stride, int logN, const cplx<T> *__restrict__ tw,
                                          int logT, const RadixPlan &rp, unsigned char *smem, int logS,
-                                         bool zero_mid = false) {
+                                         bool zero_mid = false, bool first_done = false) {
     if constexpr (kLds)
         fft_dif(buf, ns, stride, logN, tw, logT, rp, zero_mid);
     else
-        fft_dif_staged(buf, ns, stride, logN, tw, logT, rp, zero_mid, reinterpret_cast<cplx<T> *>(smem), logS);
+        fft_dif_staged(buf, ns, stride, logN, tw, logT, rp, zero_mid, reinterpret_cast<cplx<T> *>(smem), logS,
+                       first_done);
 }
+
+// whether a transform's first pass runs in global memory and can be fused into the
+// stage that produces its input (fft_first_pass_from)
+__host__ __device__ constexpr bool fuse_first(bool lds, const RadixPlan &rp) { return !lds && rp.nat == 1; }
 
 struct FastCfg {
     int nsig, threads;
@@ -176,13 +181,21 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t
     //    the odd extension u (length 2n) of h = hz * s_d that they give: u(q) at double
     //    n + q of the signal's buffer, i.e. n complex points from double n on (under the
     //    bank swizzle).  The DCT's own FFT data (doubles [0, n)) is not overwritten.
+    //    When the DST-I's first pass runs in global memory, u is never stored: the DCT's
+    //    outputs go to sd (LDS) only, and that pass builds its input points from them.
     const int strideB = BD / 2;   // complex doubles per signal
     cplx<double> *Bc = reinterpret_cast<cplx<double> *>(big);
+    constexpr RadixPlan rpB = fast_plan(kLds, logn, kLogSD, kPlanSig, nthr);
+    constexpr bool kFuseB = fuse_first(kLds, rpB);
     for (int g = tid; g < ns * (n / 2 + 1); g += nthr) {
         const int s = g / (n / 2 + 1), k = g % (n / 2 + 1);
         TD Xk, XNk;
         dct2_post(Zf + (size_t)s * strideZ, k, logn, rpA, twd, logT, Xk, XNk);
         sd[(size_t)s * n + k] = Xk;
+        if constexpr (kFuseB) {
+            if (k > 0 && k < n / 2) sd[(size_t)s * n + n - k] = XNk;
+            continue;
+        }
         double *ub = big + (size_t)s * BD + n;
         if (k == 0) {
             ub[dslot(0)] = 0.0;
@@ -200,8 +213,19 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t
         }
     }
     __syncthreads();
-    constexpr RadixPlan rpB = fast_plan(kLds, logn, kLogSD, kPlanSig, nthr);
-    fast_fft<kLds>(Bc + n / 2, ns, strideB, logn, t.tw64, logT, rpB, smem, kLogSD);
+    if constexpr (kFuseB) {
+        // u(q), 0 <= q < 2n, from sd: the same products as above
+        auto u = [&](int s, int q) -> double {
+            const TD *sds = sd + (size_t)s * n;
+            if (q < n) return q == 0 ? 0.0 : t.hz[q] * (double)sds[q];
+            return q == n ? 0.0 : -(t.hz[2 * n - q] * (double)sds[2 * n - q]);
+        };
+        fft_first_pass_from<rpB.lr(0), double, false>(
+            Bc + n / 2, ns, strideB, logn, t.tw64, logT,
+            [&](int s, int e) { return cplx<double>{u(s, 2 * e), u(s, 2 * e + 1)}; });
+        __syncthreads();
+    }
+    fast_fft<kLds>(Bc + n / 2, ns, strideB, logn, t.tw64, logT, rpB, smem, kLogSD, false, kFuseB);
 
     // 3. c = DST-I(h), times the window deconvolution; written as the odd
     //    extension q (length 4n, zero for n <= l <= 3n) in doubles [0, n) and (3n, 4n)
@@ -463,6 +487,9 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_adj(PlanTables t
         }
     }
     __syncthreads();
+    // (the grid DST's first pass is not fused into the spread as the forward's DST-I is
+    // into its producer: each grid value would be computed for both of its places in the
+    // odd extension, and that cost what the saved pass gained)
     cplx<double> *Bc = reinterpret_cast<cplx<double> *>(big);
     const int strideB = BD / 2;
     constexpr RadixPlan rpC = fast_plan(kLds, logn + 1, kLogSD, kPlanSig, nthr);

@@ -12,8 +12,9 @@
 // `stride` complex elements apart) are transformed by one call.  The buffer
 // may live in LDS or in global scratch (fft_dif_staged: one pass in global
 // memory, then LDS-sized sub-transforms staged through LDS and stored back in
-// natural order); callers pass pointers whose address space the compiler can
-// see through the inlining (LDS or global), never a generic one.
+// natural order; that first pass may instead run inside the stage that makes the
+// input, fft_first_pass_from); callers pass pointers whose address space the
+// compiler can see through the inlining (LDS or global), never a generic one.
 #pragma once
 
 #include "common.h"
@@ -210,6 +211,43 @@ __device__ __forceinline__ void buf_st(cplx<T> *buf, int e, cplx<T> a) {
     *reinterpret_cast<cplx<T> *>(reinterpret_cast<char *>(buf) + (uint64_t)((uint32_t)e * (uint32_t)sizeof(cplx<T>))) = a;
 }
 
+// Twiddles of a DIF butterfly of radix R = 2^LR at offset j in a sub-transform of
+// length L = 2^logL (j > 0 possible only when L > R): x[r] *= w^r, w = exp(-2 pi i j / L).
+// w, w^4 and w^8 come from the table and the rest from at most three products
+// (w^r = w^(r mod 4) w^(r - r mod 4)), so a radix-16 butterfly reads 3 table entries
+// instead of 15 (the table reads, shared by every workgroup through L2, bounded the
+// passes at large n).
+template <int LR, typename T>
+__device__ __forceinline__ void dif_twiddle(cplx<T> *x, int j, int logL, const cplx<T> *tw, int logNtw) {
+    constexpr int R = 1 << LR;
+    const int sh = logNtw - logL;
+    const cplx<T> w1 = tw[j << sh];
+    if constexpr (R == 2) {
+        x[1] = cmul(x[1], w1);
+    } else {
+        const cplx<T> w2 = cmul(w1, w1);
+        const cplx<T> lo[4] = {cplx<T>{T(1), T(0)}, w1, w2, cmul(w2, w1)};
+        if constexpr (R == 4) {
+#pragma unroll
+            for (int r = 1; r < 4; ++r) x[r] = cmul(x[r], lo[r]);
+        } else {
+            const cplx<T> w4 = tw[(4 * j) << sh];
+            cplx<T> hi[4] = {cplx<T>{T(1), T(0)}, w4, w4, w4};
+            if constexpr (R == 16) {
+                const cplx<T> w8 = tw[(8 * j) << sh];
+                hi[2] = w8;
+                hi[3] = cmul(w8, w4);
+            }
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const cplx<T> wr = (r >> 2) == 0 ? lo[r & 3]
+                                   : ((r & 3) == 0 ? hi[r >> 2] : cmul(lo[r & 3], hi[r >> 2]));
+                x[r] = cmul(x[r], wr);
+            }
+        }
+    }
+}
+
 // ZMID: the first pass of a transform whose input is zero on its middle half
 // (points [N/4, 3N/4)); with radix R >= 4 those are the butterfly inputs
 // r in [R/4, 3R/4), which are taken as zero instead of read.
@@ -247,10 +285,8 @@ __device__ __forceinline__ void fft_pass(cplx<T> *buf, int nsig, int stride, int
         }
         dft_reg<LR>(x);
         if (logm > 0) {
-            // twiddles w^r, w = exp(-2 pi i j / L): w, w^4 and w^8 come from the table and
-            // the rest from at most three products (w^r = w^(r mod 4) w^(r - r mod 4)), so a
-            // radix-16 butterfly reads 3 table entries instead of 15 (the table reads,
-            // shared by every workgroup through L2, bounded the passes at large n)
+            // twiddles w^r, w = exp(-2 pi i j / L), as in dif_twiddle (written out here:
+            // through the helper, the kernels built on these passes spilled)
             const int sh = logNtw - logL;
             const cplx<T> w1 = tw[j << sh];
             if constexpr (R == 2) {
@@ -285,6 +321,40 @@ __device__ __forceinline__ void fft_pass(cplx<T> *buf, int nsig, int stride, int
             else
                 sig[a ^ roff[r]] = x[r];
         }
+    }
+}
+
+// The first pass of a transform in global memory, fused into the stage that makes
+// its input: in(s, e) returns input point e of signal s (natural order), and the
+// pass's outputs go where fft_pass<LR, T, ZMID, true> would have left them, so the
+// input itself is never stored.  With ZMID, in() is not called for the zero middle.
+// fft_dif_staged(..., first_done = true) then runs the remaining passes.  in() must
+// not read the buffer's other positions' (partly overwritten) contents; the caller
+// barriers after.
+template <int LR, typename T, bool ZMID, typename In>
+__device__ __forceinline__ void fft_first_pass_from(cplx<T> *buf, int nsig, int stride, int logN,
+                                                    const cplx<T> *__restrict__ tw, int logNtw, In in) {
+    constexpr int R = 1 << LR;
+    const int logm = logN - LR, m = 1 << logm;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    int roff[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) roff[r] = fft_slot<T>(r << logm);
+    for (int g = tid; g < (nsig << logm); g += nthr) {
+        const int s = g >> logm, j = g & (m - 1);
+        const int a = fft_slot<T>(j), sb = s * stride;
+        cplx<T> x[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (ZMID && R >= 4 && r >= R / 4 && r < 3 * R / 4)
+                x[r] = cplx<T>{T(0), T(0)};
+            else
+                x[r] = in(s, j + (r << logm));
+        }
+        dft_reg<LR>(x);
+        if (logm > 0) dif_twiddle<LR>(x, j, logN, tw, logNtw);
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf_st(buf, sb + (a ^ roff[r]), x[r]);
     }
 }
 
@@ -330,13 +400,18 @@ __device__ __forceinline__ void fft_dif(cplx<T> *buf, int nsig, int stride, int 
 // splits as fft_slot(qL + e) = fft_slot(qL) ^ fft_slot(e) (fft_slot is linear and
 // the two have no bits in common), so a staged sub-transform keeps the bank
 // swizzle of a transform of length L.  zero_mid as for fft_dif (the staged copy
-// of an unwritten middle is never read).
+// of an unwritten middle is never read).  first_done: the first pass has run
+// already (fft_first_pass_from; only for a plan with a pass in global memory).
 template <typename T>
 __device__ __forceinline__ void fft_dif_staged(cplx<T> *buf, int nsig, int stride, int logN,
                                                const cplx<T> *__restrict__ tw, int logNtw, const RadixPlan &rp,
-                                               bool zero_mid, cplx<T> *stage, int logS) {
+                                               bool zero_mid, cplx<T> *stage, int logS, bool first_done = false) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     int logL = logN, i = 0;
+    if (first_done) {   // the first pass ran fused into the input's producer (fft_first_pass_from)
+        logL -= rp.lr(0);
+        i = 1;
+    }
     for (; i < rp.np && logL > logS; ++i) {
         const int lr = rp.lr(i);
         if (i == 0 && zero_mid) {
