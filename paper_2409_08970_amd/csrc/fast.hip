@@ -53,6 +53,8 @@ __host__ __device__ constexpr int big_doubles(int n) {
 // threads per workgroup and the most signals one workgroup transforms, per n = 2^logn
 // (both compile-time constants of the kernels; the host may pick fewer signals)
 __host__ __device__ constexpr int fast_threads(int logn) { return logn <= 8 ? 256 : 1024; }
+// exact rows summed together by the one-signal-per-workgroup kernels (forward)
+constexpr int kExactRows = 8;
 __host__ __device__ constexpr int fast_nsig_max(int logn) {
     const int n = 1 << logn, thr = fast_threads(logn);
     int ns = n <= 256 ? 1024 / n : 4096 / n;
@@ -300,30 +302,65 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t
     //    is split over wpp waves when there are fewer pairs than waves; the partial
     //    sums are added in a fixed order
     const int wave = tid >> 6, lane = tid & 63, nwave = nthr >> 6;
-    const int pairs = ns * nd;
-    const int wpp = (pairs > 0 && pairs < nwave) ? nwave / pairs : 1;
-    double *part = dres + (size_t)nsig * nd;   // [pairs * wpp <= nwave] partial sums
-    for (int it = wave; it < pairs * wpp; it += nwave) {
-        const int pr = it / wpp, c = it % wpp;
-        const int s = pr / nd, r = pr % nd;
-        const double *D = t.direct + (size_t)r * n;
-        const TD *sds = sd + (size_t)s * n;
-        double acc = 0.0;
-        for (int j = c * 64 + lane; j < n; j += wpp * 64) acc += D[j] * (double)sds[j];
-        acc = wave_sum(acc);
-        if (lane == 0) {
-            if (wpp == 1)
-                dres[pr] = acc;
-            else
-                part[it] = acc;
+    if (kPlanSig == 1 && nd > nwave) {
+        // one signal per workgroup (large n) and more rows than waves: every thread
+        // takes its share of the j for kExactRows rows at once, so that many
+        // independent loads are in flight (one wave per row left a long chain of
+        // dependent loads per wave, in unequal rounds); the waves' partial sums,
+        // [kExactRows][nwave] after dres, are added in a fixed order.  (With fewer
+        // rows the split below already keeps every wave busy.)
+        double *part = dres + nd;
+        for (int r0 = 0; r0 < nd; r0 += kExactRows) {
+            const int nr = nd - r0 < kExactRows ? nd - r0 : kExactRows;
+            double acc[kExactRows];
+#pragma unroll
+            for (int q = 0; q < kExactRows; ++q) acc[q] = 0.0;
+#pragma unroll 2
+            for (int j = tid; j < n; j += nthr) {
+                const double xj = (double)sd[j];
+#pragma unroll
+                for (int q = 0; q < kExactRows; ++q)
+                    if (q < nr) acc[q] += t.direct[(size_t)(r0 + q) * n + j] * xj;
+            }
+#pragma unroll
+            for (int q = 0; q < kExactRows; ++q) {
+                const double a = wave_sum(acc[q]);
+                if (lane == 0 && q < nr) part[q * nwave + wave] = a;
+            }
+            __syncthreads();
+            if (tid < nr) {
+                double sum = 0.0;
+                for (int v = 0; v < nwave; ++v) sum += part[tid * nwave + v];
+                dres[r0 + tid] = sum;
+            }
+            __syncthreads();
         }
-    }
-    if (wpp > 1) {
-        __syncthreads();
-        for (int pr = tid; pr < pairs; pr += nthr) {
+    } else {
+        const int pairs = ns * nd;
+        const int wpp = (pairs > 0 && pairs < nwave) ? nwave / pairs : 1;
+        double *part = dres + (size_t)nsig * nd;   // [pairs * wpp <= nwave] partial sums
+        for (int it = wave; it < pairs * wpp; it += nwave) {
+            const int pr = it / wpp, c = it % wpp;
+            const int s = pr / nd, r = pr % nd;
+            const double *D = t.direct + (size_t)r * n;
+            const TD *sds = sd + (size_t)s * n;
             double acc = 0.0;
-            for (int c = 0; c < wpp; ++c) acc += part[pr * wpp + c];
-            dres[pr] = acc;
+            for (int j = c * 64 + lane; j < n; j += wpp * 64) acc += D[j] * (double)sds[j];
+            acc = wave_sum(acc);
+            if (lane == 0) {
+                if (wpp == 1)
+                    dres[pr] = acc;
+                else
+                    part[it] = acc;
+            }
+        }
+        if (wpp > 1) {
+            __syncthreads();
+            for (int pr = tid; pr < pairs; pr += nthr) {
+                double acc = 0.0;
+                for (int c = 0; c < wpp; ++c) acc += part[pr * wpp + c];
+                dres[pr] = acc;
+            }
         }
     }
     __syncthreads();
@@ -590,7 +627,9 @@ FastCfg fast_config(const dctplus_plan_s *p, int cfg = 0, int64_t batch = 0) {
         while (ns > 1 && (batch + ns / 2 - 1) / (ns / 2) <= ncu) ns >>= 1;
     }
     c.nsig = ns;
-    c.lds = stage + (size_t)ns * ((c.big_in_lds ? per_big : 0) + per_small) + 64 + 8 * 16;   // + exact-row partials
+    // + exact-row partials: [kExactRows][16 waves] in the one-signal kernels, else 16
+    const size_t partials = 8 * (fast_nsig_max(p->logn) == 1 ? kExactRows * 16 : 16);
+    c.lds = stage + (size_t)ns * ((c.big_in_lds ? per_big : 0) + per_small) + 64 + partials;
     c.lds_max = (size_t)lds_max;
     return c;
 }

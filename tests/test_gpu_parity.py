@@ -404,6 +404,40 @@ def test_fast_route_exact_row_threshold(n):
         Plan(4096, rho, workloads.unit_vector(np.random.default_rng(1), 4096), route="fast", direct_kappa=1e-9)
 
 
+@pytest.mark.parametrize("n,dtype", [(4096, "f32"), (8192, "f32"), (4096, "f64")])
+def test_fast_many_exact_rows_one_signal_per_workgroup(n, dtype):
+    """The FAST kernels that hold one signal per workgroup (n >= 4096) sum the exact
+    rows a group of eight at a time, every thread taking its share of the samples.
+    Lowering direct_kappa makes dozens of rows exact (several groups and a ragged
+    last one); forward and adjoint against the semi-oracle."""
+    _torch()
+    from paper_2409_08970_amd import _binding as B
+    rho, v = case(n, "dense")
+    p, nd = None, 0
+    for kappa in np.geomspace(1e3, 1.0, 25):
+        try:
+            q = make_plan(n, rho, v, "fast", dtype=dtype, direct_kappa=float(kappa))
+        except B.DctPlusError:                     # more exact rows than the kernels hold
+            break
+        if p is not None:
+            p.close()
+        p, nd = q, int(q.info["counts"][1])
+        if nd >= 17 and nd % 8 != 0:
+            break
+    assert p is not None and nd >= 17 and nd % 8 != 0, nd
+    g = np.random.default_rng(n + 7)
+    x = g.standard_normal((6, n))
+    yin = g.standard_normal((6, n))
+    tol = TOL32 if dtype == "f32" else TOL_FAST64 * n / 4096
+    io = np.float32 if dtype == "f32" else np.float64
+    y = run(p, x.astype(io))
+    xa = run(p, yin.astype(io), adjoint=True)
+    p.close()
+    sp = oracle.semi_plan(n, rho, v)
+    assert relerr(y, oracle.semi_forward(n, rho, v, x.astype(io).astype(np.float64), sp)) <= tol, nd
+    assert relerr(xa, oracle.semi_adjoint(n, rho, v, yin.astype(io).astype(np.float64), sp)) <= tol, nd
+
+
 @pytest.mark.parametrize("route", ["dense", "gft"])
 @pytest.mark.parametrize("n", [4, 8, 16, 32, 64, 128, 256, 1024])
 @pytest.mark.parametrize("kind", ["dense", "loopn", "edge", "negative"])
