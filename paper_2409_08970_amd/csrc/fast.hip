@@ -53,7 +53,7 @@ __host__ __device__ constexpr int big_doubles(int n) {
 // threads per workgroup and the most signals one workgroup transforms, per n = 2^logn
 // (both compile-time constants of the kernels; the host may pick fewer signals)
 __host__ __device__ constexpr int fast_threads(int logn) { return logn <= 8 ? 256 : 1024; }
-// exact rows summed together by the one-signal-per-workgroup kernels (forward)
+// most exact rows summed together by the one-signal-per-workgroup kernels (forward)
 constexpr int kExactRows = 8;
 __host__ __device__ constexpr int fast_nsig_max(int logn) {
     const int n = 1 << logn, thr = fast_threads(logn);
@@ -302,39 +302,50 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t
     //    is split over wpp waves when there are fewer pairs than waves; the partial
     //    sums are added in a fixed order
     const int wave = tid >> 6, lane = tid & 63, nwave = nthr >> 6;
-    if (kPlanSig == 1 && nd > nwave) {
-        // one signal per workgroup (large n) and more rows than waves: every thread
-        // takes its share of the j for kExactRows rows at once, so that many
-        // independent loads are in flight (one wave per row left a long chain of
-        // dependent loads per wave, in unequal rounds); the waves' partial sums,
-        // [kExactRows][nwave] after dres, are added in a fixed order.  (With fewer
-        // rows the split below already keeps every wave busy.)
-        double *part = dres + nd;
-        for (int r0 = 0; r0 < nd; r0 += kExactRows) {
-            const int nr = nd - r0 < kExactRows ? nd - r0 : kExactRows;
-            double acc[kExactRows];
+    if (kPlanSig == 1) {
+        // one signal per workgroup (large n): every thread takes its share of the j
+        // for KR rows at once, so that many independent loads are in flight (one wave
+        // per row was a long chain of dependent loads); the waves' partial sums,
+        // [KR][nwave] after dres, are added in a fixed order
+        auto exact_rows = [&](auto kr) {
+            constexpr int KR = decltype(kr)::value;
+            double *part = dres + nd;
+            for (int r0 = 0; r0 < nd; r0 += KR) {
+                const int nr = nd - r0 < KR ? nd - r0 : KR;
+                // rows past the last are clamped to it (read, never stored): no branch
+                // around the loads, which keeps them all in flight together
+                const double *Dq[KR];
 #pragma unroll
-            for (int q = 0; q < kExactRows; ++q) acc[q] = 0.0;
-#pragma unroll 2
-            for (int j = tid; j < n; j += nthr) {
-                const double xj = (double)sd[j];
+                for (int q = 0; q < KR; ++q) Dq[q] = t.direct + (size_t)(q < nr ? r0 + q : nd - 1) * n;
+                double acc[KR];
 #pragma unroll
-                for (int q = 0; q < kExactRows; ++q)
-                    if (q < nr) acc[q] += t.direct[(size_t)(r0 + q) * n + j] * xj;
-            }
+                for (int q = 0; q < KR; ++q) acc[q] = 0.0;
+#pragma unroll 4
+                for (int j = tid; j < n; j += nthr) {
+                    const double xj = (double)sd[j];
 #pragma unroll
-            for (int q = 0; q < kExactRows; ++q) {
-                const double a = wave_sum(acc[q]);
-                if (lane == 0 && q < nr) part[q * nwave + wave] = a;
+                    for (int q = 0; q < KR; ++q) acc[q] += Dq[q][j] * xj;
+                }
+#pragma unroll
+                for (int q = 0; q < KR; ++q) {
+                    const double a = wave_sum(acc[q]);
+                    if (lane == 0 && q < nr) part[q * nwave + wave] = a;
+                }
+                __syncthreads();
+                if (tid < nr) {
+                    double sum = 0.0;
+                    for (int v = 0; v < nwave; ++v) sum += part[tid * nwave + v];
+                    dres[r0 + tid] = sum;
+                }
+                __syncthreads();
             }
-            __syncthreads();
-            if (tid < nr) {
-                double sum = 0.0;
-                for (int v = 0; v < nwave; ++v) sum += part[tid * nwave + v];
-                dres[r0 + tid] = sum;
-            }
-            __syncthreads();
-        }
+        };
+        if (nd <= 2)
+            exact_rows(std::integral_constant<int, 2>{});
+        else if (nd <= 4)
+            exact_rows(std::integral_constant<int, 4>{});
+        else
+            exact_rows(std::integral_constant<int, kExactRows>{});
     } else {
         const int pairs = ns * nd;
         const int wpp = (pairs > 0 && pairs < nwave) ? nwave / pairs : 1;
