@@ -592,6 +592,7 @@ void dctplus_plan_destroy(dctplus_plan_t p) {
     if (hipGetDevice(&cur) == hipSuccess && cur != p->device) (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
     if (p->t.direct) (void)hipFree(p->t.direct);
+    if (p->t.direct32) (void)hipFree(p->t.direct32);
     if (p->t.mt32) (void)hipFree(p->t.mt32);
     if (p->t.mt16) (void)hipFree(p->t.mt16);
     if (p->t.mt64) (void)hipFree(p->t.mt64);

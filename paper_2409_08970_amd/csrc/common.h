@@ -53,6 +53,8 @@ struct PlanTables {
                         //   is the weight of bin blo(P) + k, blo(P) = max(0, ((P - w/2 - 3) >> 1) + 1),
                         //   with the odd-extension folds of P near 0 and 2n merged in
     double *direct;     // [ndirect * n] exact rows a_i z_j / (mu_i - lambda_j)
+    float *direct32;    // [ndirect * n] the same rows rounded to FP32 (plans with FP32 signals:
+                        //   half the bytes for the kernels that read them per signal)
     int32_t *direct_row;// [ndirect] output row of each direct slot
     int32_t *rowOfBin;  // [n]    output row of the NUFFT root in bin b, or -1
     int32_t *rowOfK;    // [n]    output row of deflated index k, or -1

@@ -55,6 +55,16 @@ __host__ __device__ constexpr int big_doubles(int n) {
 __host__ __device__ constexpr int fast_threads(int logn) { return logn <= 8 ? 256 : 1024; }
 // most exact rows summed together by the one-signal-per-workgroup kernels (forward)
 constexpr int kExactRows = 8;
+
+// the exact-row table in the kernels' internal type (FP32 plans keep an FP32 copy:
+// the rows are read once per signal, and the sums stay in FP64)
+template <typename TD>
+__device__ __forceinline__ const TD *direct_rows(const PlanTables &t) {
+    if constexpr (sizeof(TD) == 4)
+        return t.direct32;
+    else
+        return t.direct;
+}
 __host__ __device__ constexpr int fast_nsig_max(int logn) {
     const int n = 1 << logn, thr = fast_threads(logn);
     int ns = n <= 256 ? 1024 / n : 4096 / n;
@@ -314,9 +324,9 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t
                 const int nr = nd - r0 < KR ? nd - r0 : KR;
                 // rows past the last are clamped to it (read, never stored): no branch
                 // around the loads, which keeps them all in flight together
-                const double *Dq[KR];
+                const TD *Dq[KR];
 #pragma unroll
-                for (int q = 0; q < KR; ++q) Dq[q] = t.direct + (size_t)(q < nr ? r0 + q : nd - 1) * n;
+                for (int q = 0; q < KR; ++q) Dq[q] = direct_rows<TD>(t) + (size_t)(q < nr ? r0 + q : nd - 1) * n;
                 double acc[KR];
 #pragma unroll
                 for (int q = 0; q < KR; ++q) acc[q] = 0.0;
@@ -324,7 +334,7 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t
                 for (int j = tid; j < n; j += nthr) {
                     const double xj = (double)sd[j];
 #pragma unroll
-                    for (int q = 0; q < KR; ++q) acc[q] += Dq[q][j] * xj;
+                    for (int q = 0; q < KR; ++q) acc[q] += (double)Dq[q][j] * xj;
                 }
 #pragma unroll
                 for (int q = 0; q < KR; ++q) {
@@ -353,10 +363,10 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_fwd(PlanTables t
         for (int it = wave; it < pairs * wpp; it += nwave) {
             const int pr = it / wpp, c = it % wpp;
             const int s = pr / nd, r = pr % nd;
-            const double *D = t.direct + (size_t)r * n;
+            const TD *D = direct_rows<TD>(t) + (size_t)r * n;
             const TD *sds = sd + (size_t)s * n;
             double acc = 0.0;
-            for (int j = c * 64 + lane; j < n; j += wpp * 64) acc += D[j] * (double)sds[j];
+            for (int j = c * 64 + lane; j < n; j += wpp * 64) acc += (double)D[j] * (double)sds[j];
             acc = wave_sum(acc);
             if (lane == 0) {
                 if (wpp == 1)
@@ -583,7 +593,7 @@ __global__ void __launch_bounds__(fast_threads(LOGN), 4) k_fast_adj(PlanTables t
         const TIO *ys = y + (s0 + s) * n;   // deflated rows come straight from the input
         const int rk = t.rowOfK[j];
         if (rk >= 0) v += (double)(TD)ys[rk];
-        for (int r = 0; r < nd; ++r) v += t.direct[(size_t)r * n + j] * ydir[(size_t)s * nd + r];
+        for (int r = 0; r < nd; ++r) v += (double)direct_rows<TD>(t)[(size_t)r * n + j] * ydir[(size_t)s * nd + r];
         big[(size_t)s * BD + 2 * n + j] = v;
     }
     __syncthreads();
@@ -700,6 +710,8 @@ dctplus_status fast_apply(dctplus_plan_s *p, const void *in, void *out, int64_t 
     }
     if (blocks > 0x7fffffff) return fail(DCTPLUS_EINVAL, "batch too large");
     const dim3 grid((unsigned)blocks);
+    if (p->t.ndirect > 0 && (p->dtype == DCTPLUS_F64 ? p->t.direct == nullptr : p->t.direct32 == nullptr))
+        return fail(DCTPLUS_EINVAL, "plan has %d exact rows but no table for them", p->t.ndirect);
     dctplus_status st;
     if (p->dtype == DCTPLUS_F64)
         st = c.big_in_lds ? launch_fast<double, double, true>(p, c, grid, in, out, batch, adjoint, scratch, s)

@@ -391,6 +391,12 @@ __global__ void k_direct(PlanTables t) {
     }
 }
 
+// The exact rows rounded to FP32 (for plans with FP32 signals).
+__global__ void k_direct32(const double *__restrict__ d, float *__restrict__ d32, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        d32[i] = (float)d[i];
+}
+
 // Window transform 1 / phi_hat(l h), h = pi / 2n, by Gauss-Legendre quadrature
 // (nodes from Newton's method on the Legendre recurrence, recomputed by every
 // workgroup; each workgroup then covers its own range of frequencies l).
@@ -584,6 +590,17 @@ dctplus_status plan_build(dctplus_plan_s *p, const double *v_host, hipStream_t s
         }
         hipLaunchKernelGGL(k_direct, dim3(t.ndirect), dim3(256), 0, s, t);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "direct rows");
+        if (p->dtype != DCTPLUS_F64) {
+            const int64_t count = (int64_t)t.ndirect * n;
+            if ((e = hipMalloc(&t.direct32, sizeof(float) * (size_t)count)) != hipSuccess) {
+                t.direct32 = nullptr;
+                (void)hipGetLastError();
+                return fail(DCTPLUS_ENOMEM, "hipMalloc for %d FP32 direct rows failed", t.ndirect);
+            }
+            const int64_t blocks = (count + 255) / 256 < 4096 ? (count + 255) / 256 : 4096;
+            hipLaunchKernelGGL(k_direct32, dim3((unsigned)blocks), dim3(256), 0, s, t.direct, t.direct32, count);
+            if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "FP32 direct rows");
+        }
     }
     if ((p->route == DCTPLUS_ROUTE_DENSE || p->route == DCTPLUS_ROUTE_GFT) && !p->defer_dense) {
         dctplus_status ds = dense_build(p, s);
